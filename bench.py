@@ -1,0 +1,301 @@
+#!/usr/bin/env python3
+"""Benchmark of brute-force dedispersion on one MI355X.
+
+Default workload: 256 uneven beams (per beam, seeded: 256/512/1024/1536
+channels over 1270-1570 MHz, 512-4096 DM trials in steps of 0.25, 8000-20000
+output samples, 50 us sampling, FP32 noise with two injected pulses), run as
+one persistent, graph-captured launch with the tile shape chosen by the
+autotuner, and compared with a loop of per-beam launches (each beam's plan
+tuned on its own).  One step = one pass over all beams; inputs are resident
+in HBM before the timed region.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DM-trial·samples/s (GB/s and % of HBM roofline), batched vs plain"
+HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
+ADD_PEAK = 157.3e12 / 2      # FP32 adds/s: 157.3 TFLOP/s counts an FMA as 2 flops; an add is 1
+T0 = time.time()
+
+
+def log(msg):
+    print(f"[bench {time.time() - T0:7.1f}s] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="batched", choices=["batched", "apertif", "lofar", "diff"])
+    ap.add_argument("--no-tune", action="store_true", help="use default variants (no autotuning)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the per-beam loop")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--beams", type=int, default=0, help="use only the first N beams (debugging)")
+    return ap.parse_args()
+
+
+def fill_noise(t, seed):
+    import torch
+
+    g = torch.Generator(device=t.device)
+    g.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
+    t.copy_(torch.randn(t.shape, generator=g, device=t.device, dtype=t.dtype))
+
+
+def inject_device(x, delta_row, t0, width, amp):
+    """x[c][t0 + delta[c] + k] += amp for k < width (x: [C][nin] on the GPU)."""
+    import torch
+
+    c = torch.arange(x.shape[0], device=x.device)
+    d = torch.from_numpy(delta_row.astype(np.int64)).to(x.device)
+    for k in range(width):
+        x[c, t0 + d + k] += amp
+
+
+def time_steps(fn, steps, warmup, stream_sync):
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    stream_sync()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    per = []
+    t_start = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        per.append((a, b))
+    e1.record()
+    stream_sync()
+    wall = time.perf_counter() - t_start
+    total_ms = e0.elapsed_time(e1)
+    launch_ms = [a.elapsed_time(b) for a, b in per]
+    return total_ms / steps, launch_ms, wall
+
+
+def cpu_baseline(beam, target_s):
+    """Time the plain oracle on a bounded sample of one beam: all channels and
+    samples, a prefix of the DM trials sized for ~target_s seconds."""
+    import oracle
+    import synth
+
+    oracle.build()
+    delta = oracle.delay_table(beam.freqs(), beam.tsamp_s, beam.dms())
+    nin = beam.nsamp + int(delta.max())
+    x = synth.noise(beam, nin)
+    # calibrate on 4 DM trials
+    t = time.perf_counter()
+    oracle.forward_f32(x, delta[:4], beam.nsamp)
+    dt4 = time.perf_counter() - t
+    nd = int(max(4, min(beam.ndm, 4 * target_s / max(dt4, 1e-6))))
+    nd = max(oracle.num_threads(), nd - nd % max(1, oracle.num_threads()))
+    nd = min(nd, beam.ndm)
+    t = time.perf_counter()
+    oracle.forward_f32(x, delta[:nd], beam.nsamp)
+    el = time.perf_counter() - t
+    return {
+        "value": nd * beam.nsamp / el,
+        "unit": "DM-trial·samples/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"one beam: {beam.nchan} channels x {beam.nsamp} samples, first {nd} of {beam.ndm} DM trials "
+                  f"(Algorithm 1 order, FP32), {el:.1f} s",
+        "seconds": el,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: beams are independent and shard by beam "
+                                   "with no exchange; run one process per GPU with a share of the beams"}))
+        sys.exit(2)
+    import torch
+
+    import paper_1601_01165_amd as dd
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    sync = torch.cuda.synchronize
+
+    wl = args.workload
+    extra = {}
+    if wl in ("batched", "apertif", "diff"):
+        k = {"batched": 3, "apertif": 1, "diff": 4}[wl]
+    else:
+        k = 2
+    beams = synth.config(k)
+    if args.beams:
+        beams = beams[: args.beams]
+    log(f"workload {wl}: {len(beams)} beam(s)")
+
+    plans, xs, outs = [], [], []
+    adds = 0
+    algo_bytes = 0
+    dm_samples = 0
+    for i, b in enumerate(beams):
+        p = dd.Plan(b.freqs(), b.tsamp_s, b.dms())
+        nin = b.nsamp + p.max_delay
+        dtype = torch.uint8 if b.dtype == "u8" else torch.float32
+        x = dd.empty_rows(1, b.nchan, nin, dtype, dev)
+        if b.dtype == "u8":
+            g = torch.Generator(device=dev)
+            g.manual_seed(b.seed)
+            v = torch.randn(x.shape, generator=g, device=dev)
+            x.copy_(torch.clamp(torch.round(128.0 + 16.0 * v), 0, 255).to(torch.uint8))
+        else:
+            fill_noise(x, b.seed)
+            delays = None
+            for j, t0 in synth.pulses(b, p.max_delay):
+                if delays is None:
+                    delays = p.delays()
+                inject_device(x[0], delays[j], t0, b.pulse_width, b.pulse_amp)
+        out = dd.empty_rows(1, b.ndm, b.nsamp, torch.int32 if b.dtype == "u8" else torch.float32, dev)
+        plans.append(p)
+        xs.append(x)
+        outs.append(out)
+        adds += b.nchan * b.ndm * b.nsamp
+        algo_bytes += b.nchan * nin * b.elem_bytes() + b.ndm * b.nsamp * 4 + 4 * b.nchan * b.ndm
+        dm_samples += b.ndm * b.nsamp
+        if i % 32 == 31:
+            log(f"  prepared {i + 1} beams")
+    sync()
+    log(f"inputs resident: {sum(x.numel() * x.element_size() for x in xs) / 1e9:.2f} GB in, "
+        f"{sum(o.numel() * 4 for o in outs) / 1e9:.2f} GB out")
+
+    plain = None
+    if wl == "batched":
+        batch = dd.Batch(plans, xs, outs, tune=not args.no_tune)
+        log("batch created (variant chosen)")
+        step = batch.execute
+        if not args.no_plain:
+            if not args.no_tune:
+                for i, (p, b) in enumerate(zip(plans, beams)):
+                    p.autotune(1, b.nsamp, "f32")
+                    if i % 64 == 63:
+                        log(f"  tuned {i + 1} per-beam plans")
+            ms_p, lp, _ = time_steps(batch.execute_per_beam, args.steps, args.warmup, sync)
+            plain = {"value": dm_samples / (ms_p / 1e3), "ms_per_step": ms_p}
+            log(f"plain per-beam loop: {ms_p:.3f} ms/step")
+        kernel_name = "win_persistent"
+    elif wl in ("apertif", "lofar"):
+        p, b, x, o = plans[0], beams[0], xs[0], outs[0]
+        if not args.no_tune:
+            times = p.autotune(1, b.nsamp, "u8" if b.dtype == "u8" else "f32")
+            extra["autotune_ms"] = {kk: round(v, 4) for kk, v in times.items()}
+            log(f"autotuned: {times}")
+
+        def step():
+            dd.dedisperse(x, p, nsamp=b.nsamp, out=o)
+        kernel_name = "u8_kernel" if b.dtype == "u8" else "win_kernel"
+    else:  # diff: forward + adjoint with the weight gradient over all beams
+        w = torch.ones(beams[0].nchan, device=dev)
+        p0 = plans[0]
+        xb = dd.empty_rows(len(beams), beams[0].nchan, xs[0].shape[2], torch.float32, dev)
+        for i, x in enumerate(xs):
+            xb[i].copy_(x[0])
+        g = dd.empty_rows(len(beams), beams[0].ndm, beams[0].nsamp, torch.float32, dev)
+        fill_noise(g, 5)
+        ob = dd.empty_rows(len(beams), beams[0].ndm, beams[0].nsamp, torch.float32, dev)
+        xs, outs = [xb], [ob]
+        adds *= 2
+        nin = xb.shape[2]
+
+        def step():
+            dd.dedisperse(xb, p0, w, nsamp=beams[0].nsamp, out=ob)
+            dd.adjoint(g, p0, nin, w, xb)
+        kernel_name = "win_kernel (forward + adjoint)"
+
+    log("timing")
+    ms, launch_ms, wall = time_steps(step, args.steps, args.warmup, sync)
+    value = dm_samples / (ms / 1e3)
+    kern_ms = float(np.mean(launch_ms))
+    log(f"{ms:.3f} ms/step, {value:.4e} DM-trial*samples/s")
+
+    achieved = adds / (kern_ms / 1e3)
+    roof = {
+        "bound": "alu",
+        "achieved": achieved / 1e12,
+        "peak": ADD_PEAK / 1e12,
+        "unit": "TFLOP/s",
+        "frac": achieved / ADD_PEAK,
+        "traffic": None,
+        "kernel": kernel_name,
+        "kernel_ms": kern_ms,
+        "note": "one FP32 add per (channel, DM trial, sample), the paper's flop count; peak = 157.3/2",
+    }
+    if wl == "lofar":
+        roof.update({"bound": "hbm", "achieved": algo_bytes / (kern_ms / 1e3) / 1e9, "peak": HBM_PEAK / 1e9,
+                     "unit": "GB/s", "frac": algo_bytes / (kern_ms / 1e3) / HBM_PEAK,
+                     "note": "algorithmic bytes: input once + int32 output + delay table"})
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DM-trial·samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8" if wl == "lofar" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": {
+                "batched": "256 uneven beams in one persistent graph-captured launch (256/512/1024/1536 ch, "
+                           "1270-1570 MHz, 512-4096 DMs step 0.25, 8000-20000 samples, 50 us, FP32)",
+                "apertif": "Apertif-like beam: 1024 ch 1270-1570 MHz, 2048 DMs step 0.25, 20000 samples, FP32",
+                "lofar": "LOFAR-like beam: 32 ch 134.875-141.125 MHz, 2048 DMs step 0.01, 200000 samples, u8->i32",
+                "diff": "32 Apertif-like beams, 1024 ch, 1024 DMs, 20000 samples: forward + adjoint + grad_w",
+            }[wl],
+            "beams": len(beams),
+            "dm_trial_samples_per_step": dm_samples,
+            "adds_per_step": adds,
+        },
+        "gbps": algo_bytes / (ms / 1e3) / 1e9,
+        "hbm_frac": algo_bytes / (ms / 1e3) / HBM_PEAK,
+        "valu_frac": adds / (ms / 1e3) / ADD_PEAK,
+        "gflops_paper_convention": adds / (ms / 1e3) / 1e9,
+        "realtime_factor": (1.0 / (ms / 1e3)) * (
+            beams[0].nsamp * beams[0].tsamp_s if wl != "batched" else 1.0),
+        "roofline": roof,
+    }
+    if plain:
+        line["plain_value"] = plain["value"]
+        line["plain_ms_per_step"] = plain["ms_per_step"]
+        line["batched_over_plain"] = value / plain["value"]
+    line["paper_context"] = {
+        "hd7970_apertif_2000dm": "0.08 s per 1 s of data = 5.0e8 DM-trial*samples/s (AMD HD7970, OpenCL, FP32)"}
+    line.update(extra)
+    if not args.no_cpu:
+        log("CPU oracle baseline")
+        cb_beam = beams[0]
+        line["cpu_baseline"] = cpu_baseline(cb_beam, args.cpu_seconds)
+        log(f"cpu baseline {line['cpu_baseline']['value']:.3e}")
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,310 @@
+"""Brute-force incoherent dedispersion on MI355X (gfx950).
+
+Thin Python binding of libdedisp.so (see include/dedisp.h): argument
+marshalling only, every step of the computation runs in the library's HIP
+kernels.  PyTorch supplies device memory and streams.
+
+Method: Sclocco et al., "Real-Time Dedispersion for Fast Radio Transient
+Surveys, using Auto Tuning on Many-Core Accelerators" (arXiv 1601.01165):
+delays from Section 2, Equation 1; the sum of Section 2.1, Algorithm 1.
+
+Tensors
+  input   [nbeam][nchan][nin]   float32 or uint8 on the GPU, time contiguous
+  output  [nbeam][ndm][nsamp]   float32 (int32 for uint8 input)
+Each row's byte stride must be a multiple of 16 and the base pointer 16-byte
+aligned; ``empty_rows`` allocates such tensors (a padded buffer, returned as a
+view), and inputs that do not satisfy this are copied into one.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _clib
+from ._clib import F32, I32, U8, DedispError, check
+
+__all__ = [
+    "Plan", "Batch", "DedispFunction", "DedispError", "compute_delays", "dedisperse", "dedisperse_autograd",
+    "adjoint", "empty_rows", "variant_names", "lib",
+]
+
+
+def lib():
+    return _clib.load()
+
+
+def _stream(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dt(dtype) -> int:
+    if dtype in (torch.float32, np.float32, "f32", "float32", F32):
+        return F32
+    if dtype in (torch.uint8, np.uint8, "u8", "uint8", U8):
+        return U8
+    raise ValueError(f"unsupported dtype {dtype}")
+
+
+def _esz(dtype: torch.dtype) -> int:
+    return torch.empty((), dtype=dtype).element_size()
+
+
+def padded(n: int, elem_bytes: int) -> int:
+    """Smallest row length >= n whose byte size is a multiple of 16."""
+    q = 16 // elem_bytes
+    return (n + q - 1) // q * q
+
+
+def empty_rows(nbeam: int, nrows: int, n: int, dtype=torch.float32, device="cuda", zero=False) -> torch.Tensor:
+    """A [nbeam][nrows][n] tensor whose rows start on 16-byte boundaries."""
+    stride = padded(n, _esz(dtype))
+    buf = (torch.zeros if zero else torch.empty)((nbeam, nrows, stride), dtype=dtype, device=device)
+    return buf[:, :, :n]
+
+
+def _rows_ok(t: torch.Tensor) -> bool:
+    es = t.element_size()
+    return (t.dim() == 3 and t.stride(2) == 1 and (t.stride(1) * es) % 16 == 0
+            and t.stride(0) == t.shape[1] * t.stride(1) and t.data_ptr() % 16 == 0)
+
+
+def _as_rows(t: torch.Tensor) -> torch.Tensor:
+    """t as [nbeam][rows][n] satisfying the row rules (copying if needed)."""
+    if t.dim() == 2:
+        t = t.unsqueeze(0)
+    if t.dim() != 3:
+        raise ValueError("expected a [nbeam][rows][samples] or [rows][samples] tensor")
+    if not t.is_cuda:
+        raise ValueError("tensors must be on the GPU")
+    if _rows_ok(t):
+        return t
+    r = empty_rows(t.shape[0], t.shape[1], t.shape[2], t.dtype, t.device)
+    r.copy_(t)
+    return r
+
+
+def variant_names(dtype="f32") -> list[str]:
+    L = lib()
+    d = _dt(dtype)
+    return [L.dedisp_variant_name(d, i).decode() for i in range(L.dedisp_variant_count(d))]
+
+
+def compute_delays(freq_mhz, tsamp_s: float, dms) -> np.ndarray:
+    """Host-only delay table delta[dm][chan] (Eq. 1, FP64, round half up)."""
+    f = np.ascontiguousarray(freq_mhz, np.float64)
+    d = np.ascontiguousarray(dms, np.float64)
+    out = np.empty((d.size, f.size), np.int32)
+    md = ctypes.c_int32()
+    check(lib().dedisp_compute_delays(f.size, f.ctypes.data, float(tsamp_s), d.size, d.ctypes.data,
+                                      out.ctypes.data, ctypes.byref(md)), "compute_delays")
+    return out
+
+
+class Plan:
+    """Delay table for one observing set-up and DM list, resident on the GPU."""
+
+    def __init__(self, freq_mhz, tsamp_s: float, dms):
+        L = lib()
+        f = np.ascontiguousarray(freq_mhz, np.float64)
+        d = np.ascontiguousarray(dms, np.float64)
+        h = ctypes.c_void_p()
+        check(L.dedisp_plan_create(ctypes.byref(h), f.size, f.ctypes.data, float(tsamp_s), d.size, d.ctypes.data),
+              "plan_create")
+        self._h = h
+        nc, nd, md = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(L.dedisp_plan_info(h, ctypes.byref(nc), ctypes.byref(nd), ctypes.byref(md)), "plan_info")
+        self.nchan, self.ndm, self.max_delay = nc.value, nd.value, md.value
+        self.freq_mhz, self.tsamp_s, self.dms = f.copy(), float(tsamp_s), d.copy()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dedisp_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def delays(self) -> np.ndarray:
+        out = np.empty((self.ndm, self.nchan), np.int32)
+        check(lib().dedisp_plan_delays(self._h, out.ctypes.data), "plan_delays")
+        return out
+
+    def prepare(self, dtype="f32", adjoint=False):
+        check(lib().dedisp_plan_prepare(self._h, _dt(dtype), int(bool(adjoint))), "plan_prepare")
+
+    def set_variant(self, index: int, dtype="f32"):
+        check(lib().dedisp_plan_set_variant(self._h, _dt(dtype), int(index)), "plan_set_variant")
+
+    def variant(self, dtype="f32") -> int:
+        return int(lib().dedisp_plan_variant(self._h, _dt(dtype)))
+
+    def set_adjoint_variant(self, index: int):
+        check(lib().dedisp_plan_set_adjoint_variant(self._h, int(index)), "plan_set_adjoint_variant")
+
+    def adjoint_variant(self) -> int:
+        return int(lib().dedisp_plan_adjoint_variant(self._h))
+
+    def autotune(self, nbeam: int, nsamp: int, dtype="f32", cache_path: str | None = None) -> dict:
+        """Exhaustive search over the compiled variants; returns {name: ms}."""
+        L = lib()
+        d = _dt(dtype)
+        check(L.dedisp_autotune(self._h, int(nbeam), int(nsamp), d, cache_path.encode() if cache_path else None),
+              "autotune")
+        n = L.dedisp_variant_count(d) + 1
+        ms = np.full(n, -1.0, np.float32)
+        k = L.dedisp_autotune_times(self._h, d, ms.ctypes.data, n)
+        names = variant_names(dtype) + ["direct"]
+        return {names[i]: float(ms[i]) for i in range(k)}
+
+
+def dedisperse(x: torch.Tensor, plan: Plan, w: torch.Tensor | None = None, nsamp: int | None = None,
+               out: torch.Tensor | None = None) -> torch.Tensor:
+    """out[b][dm][t] = sum_c w[c] * x[b][c][t + delta[dm][c]] (Algorithm 1)."""
+    squeeze = x.dim() == 2
+    xr = _as_rows(x)
+    nb, nc, nin = xr.shape
+    if nc != plan.nchan:
+        raise ValueError(f"input has {nc} channels, plan has {plan.nchan}")
+    if nsamp is None:
+        nsamp = nin - plan.max_delay
+    if nsamp < 1 or nin < nsamp + plan.max_delay:
+        raise ValueError(f"need nin >= nsamp + max_delay ({nsamp} + {plan.max_delay}), got {nin}")
+    dt = _dt(xr.dtype)
+    odt = torch.int32 if dt == U8 else torch.float32
+    if w is not None:
+        if dt == U8:
+            raise ValueError("weights are not supported for uint8 input")
+        w = w.detach().to(torch.float32).contiguous()
+        if w.numel() != nc or not w.is_cuda:
+            raise ValueError("weights must be a float32 GPU tensor of nchan values")
+    if out is None:
+        out = empty_rows(nb, plan.ndm, nsamp, odt, xr.device)
+    elif not _rows_ok(out) or out.dtype != odt or tuple(out.shape) != (nb, plan.ndm, nsamp):
+        raise ValueError("out must be [nbeam][ndm][nsamp] with 16-byte aligned rows")
+    check(lib().dedisp_execute(plan.handle, nb, nsamp, ctypes.c_void_p(xr.data_ptr()), dt, xr.stride(1),
+                               ctypes.c_void_p(w.data_ptr()) if w is not None else None,
+                               ctypes.c_void_p(out.data_ptr()), I32 if dt == U8 else F32, out.stride(1),
+                               _stream(xr.device)), "execute")
+    return out[0] if squeeze else out
+
+
+def adjoint(g: torch.Tensor, plan: Plan, nin: int, w: torch.Tensor | None = None, x: torch.Tensor | None = None,
+            want_grad_in: bool = True):
+    """Transpose of dedisperse.  Returns (grad_in [nbeam][nchan][nin] or None,
+    grad_w [nchan] or None); grad_w needs the forward input x."""
+    gr = _as_rows(g.to(torch.float32) if g.dtype != torch.float32 else g)
+    nb, nd, ns = gr.shape
+    if nd != plan.ndm:
+        raise ValueError(f"gradient has {nd} DM rows, plan has {plan.ndm}")
+    if w is not None:
+        w = w.detach().to(torch.float32).contiguous()
+    xr = _as_rows(x.detach()) if x is not None else None
+    gi = empty_rows(nb, plan.nchan, nin, torch.float32, gr.device) if want_grad_in else None
+    gw = torch.empty(plan.nchan, dtype=torch.float32, device=gr.device) if xr is not None else None
+    ws = None
+    nbytes = 0
+    if gw is not None:
+        nbytes = lib().dedisp_adjoint_workspace_bytes(plan.handle, nb, nin)
+        ws = torch.empty(max(nbytes, 8), dtype=torch.uint8, device=gr.device)
+    check(lib().dedisp_adjoint(plan.handle, nb, ns, nin, ctypes.c_void_p(gr.data_ptr()), gr.stride(1),
+                               ctypes.c_void_p(w.data_ptr()) if w is not None else None,
+                               ctypes.c_void_p(xr.data_ptr()) if xr is not None else None,
+                               xr.stride(1) if xr is not None else 0,
+                               ctypes.c_void_p(gi.data_ptr()) if gi is not None else None,
+                               gi.stride(1) if gi is not None else 0,
+                               ctypes.c_void_p(gw.data_ptr()) if gw is not None else None,
+                               ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, nbytes,
+                               _stream(gr.device)), "adjoint")
+    return gi, gw
+
+
+class DedispFunction(torch.autograd.Function):
+    """Differentiable dedispersion: forward = dedisperse, backward = adjoint.
+
+    apply(x, w, plan, nsamp) with x [nbeam][nchan][nin] float32 and w [nchan]
+    float32 (or None).  Gradients flow to x (gather-form adjoint scaled by w)
+    and to w (sum over beams and samples of x times the adjoint)."""
+
+    @staticmethod
+    def forward(ctx, x, w, plan, nsamp):
+        out = dedisperse(x, plan, w, nsamp)
+        ctx.plan = plan
+        ctx.nin = x.shape[-1]
+        ctx.squeeze = x.dim() == 2
+        ctx.save_for_backward(x, w if w is not None else torch.empty(0, device=x.device))
+        ctx.has_w = w is not None
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        x, w = ctx.saved_tensors
+        w = w if ctx.has_w else None
+        need_x = ctx.needs_input_grad[0]
+        need_w = ctx.has_w and ctx.needs_input_grad[1]
+        gi, gw = adjoint(g, ctx.plan, ctx.nin, w, x if need_w else None, want_grad_in=need_x)
+        if gi is not None and ctx.squeeze:
+            gi = gi[0]
+        return gi, gw, None, None
+
+
+def dedisperse_autograd(x, plan, w=None, nsamp=None):
+    if nsamp is None:
+        nsamp = x.shape[-1] - plan.max_delay
+    return DedispFunction.apply(x, w, plan, nsamp)
+
+
+class Batch:
+    """Many independent beams (each its own plan, sizes and buffers) run as one
+    persistent, graph-captured launch (execute) or as a per-beam launch loop
+    (execute_per_beam)."""
+
+    def __init__(self, plans, inputs, outputs, nsamps=None, weights=None, tune=False):
+        L = lib()
+        n = len(plans)
+        if not (len(inputs) == len(outputs) == n) or n < 1:
+            raise ValueError("plans, inputs and outputs must have the same non-zero length")
+        xs = [_as_rows(x) for x in inputs]
+        for x, o in zip(xs, outputs):
+            if x.shape[0] != 1 or o.dim() != 3 or o.shape[0] != 1 or not _rows_ok(o):
+                raise ValueError("batch inputs/outputs are single beams with 16-byte aligned rows")
+        if nsamps is None:
+            nsamps = [o.shape[2] for o in outputs]
+        self._keep = (plans, xs, outputs, weights)
+        arr = lambda typ, vals: (typ * n)(*vals)  # noqa: E731
+        hp = arr(ctypes.c_void_p, [p.handle.value for p in plans])
+        ns = arr(ctypes.c_int32, nsamps)
+        din = arr(ctypes.c_void_p, [x.data_ptr() for x in xs])
+        ist = arr(ctypes.c_int64, [x.stride(1) for x in xs])
+        dw = arr(ctypes.c_void_p, [w.data_ptr() for w in weights]) if weights is not None else None
+        dout = arr(ctypes.c_void_p, [o.data_ptr() for o in outputs])
+        ost = arr(ctypes.c_int64, [o.stride(1) for o in outputs])
+        h = ctypes.c_void_p()
+        check(L.dedisp_batch_create(ctypes.byref(h), n, hp, ns, din, ist, dw, dout, ost, int(bool(tune))),
+              "batch_create")
+        self._h = h
+
+    def execute(self):
+        check(lib().dedisp_execute_batched(self._h, _stream()), "execute_batched")
+
+    def execute_per_beam(self):
+        check(lib().dedisp_execute_per_beam(self._h, _stream()), "execute_per_beam")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dedisp_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

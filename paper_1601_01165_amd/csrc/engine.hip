@@ -1,0 +1,587 @@
+// gfx950 kernels for brute-force incoherent dedispersion.
+//
+// Forward map (Sclocco et al., arXiv 1601.01165, Section 2.1, Algorithm 1):
+//   out[b][r][t] = sum over input rows c, ascending, of w[c] * in[b][c][t + delta(r, c)]
+// with r a DM trial and c a channel.  The adjoint is the same map with the
+// roles swapped (r a channel, c a DM trial, delay' = pad - delay, input rows
+// read as zero outside the output range), so one tile engine serves both.
+//
+// Parallel structure (Section 2.2): each work item owns (output row, time)
+// pairs; a block owns a tile of output rows x time samples, so the input rows
+// it needs are shared by all its rows (the paper's DM-direction reuse through
+// local memory).  On gfx950:
+//   * a block stages, for cc input rows at a time, the window
+//     [t0 + stage_base(c), t0 + stage_base(c) + stage_len(c)) of each row into
+//     LDS with 16-byte loads (all 16-byte aligned);
+//   * each wave owns dpw output rows and 64*tp samples, each lane tp
+//     consecutive samples.  Per input row the lane copies its window of
+//     samples from LDS into registers once (16-byte LDS reads) and every one
+//     of its dpw rows adds tp window registers, selected through VGPR index
+//     mode with the row's delay offset (see gen_win_asm.py).  One LDS byte
+//     thus feeds several adds, which is what keeps the add units busy: an LDS
+//     read per add would cap the rate at the LDS bandwidth.
+//   * blocks are remapped so that the blocks of one time tile run on the same
+//     XCD, sharing that XCD's L2 for the input window.
+//   * accumulation order per output is ascending input row with one rounding
+//     per term, the order of Algorithm 1, so the FP32 results are those of a
+//     sequential FP32 loop.
+#include "internal.h"
+
+namespace dd {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+#include "win_asm.inc"
+
+#define LDS_AS __attribute__((address_space(3)))
+
+// Blocks are dispatched round-robin over the 8 XCDs.  Give each XCD a
+// contiguous range of work items (time-major, output rows fastest).
+__device__ __forceinline__ int xcd_remap(int L, int N) {
+  const int q = N >> 3, r = N & 7;
+  const int x = L & 7, k = L >> 3;
+  return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// ---------------------------------------------------------------------------
+// FP32 tile engine with the register window.
+// ---------------------------------------------------------------------------
+
+// Stage input rows [c0, c0 + ncc) into LDS.  Wave w copies rows w, w + NWAVE, ...
+template <int NWAVE, int ROWCAP>
+__device__ __forceinline__ void stage_f32(float4* lds4, const float* in, const TileArgs& a, const int32_t* blk,
+                                          int c0, int ncc, int t0) {
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  for (int cl = wave; cl < ncc; cl += NWAVE) {
+    const int sb = blk[2 * (c0 + cl)];
+    const int sl = blk[2 * (c0 + cl) + 1];
+    const float* src = in + (int64_t)(c0 + cl) * a.in_stride + a.in_shift;
+    const int u0 = t0 + sb;
+    float4* dst = lds4 + cl * (ROWCAP / 4);
+    const int nv = sl >> 2;
+#pragma unroll 4
+    for (int v = lane; v < nv; v += 64) {
+      const int u = u0 + 4 * v;
+      float4 x;
+      if (u >= a.in_lo && u + 4 <= a.in_hi) {
+        x = *reinterpret_cast<const float4*>(src + u);
+      } else {
+        x.x = (u + 0 >= a.in_lo && u + 0 < a.in_hi) ? src[u + 0] : 0.f;
+        x.y = (u + 1 >= a.in_lo && u + 1 < a.in_hi) ? src[u + 1] : 0.f;
+        x.z = (u + 2 >= a.in_lo && u + 2 < a.in_hi) ? src[u + 2] : 0.f;
+        x.w = (u + 3 >= a.in_lo && u + 3 < a.in_hi) ? src[u + 3] : 0.f;
+      }
+      dst[v] = x;
+    }
+  }
+}
+
+template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, bool WEIGHTED, bool ADJ>
+__device__ __forceinline__ void win_tile(const TileArgs& a, int tt, int rt, int beam, float4* lds4) {
+  constexpr int ST = 64 * TP;
+  constexpr int DT = NWAVE * DPW;
+  constexpr int NACC = TP * DPW / 16;
+  constexpr int WI = DPW > 8 ? 8 : 4;
+  const int t0 = tt * ST;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  const int wt = rt * NWAVE + wave;
+  const float* in = static_cast<const float*>(a.in) + (int64_t)beam * a.in_beam_stride;
+  const int32_t* __restrict__ blk = a.blk + (size_t)rt * a.rows_in * 2;
+  const int32_t* __restrict__ wav = a.wav + (size_t)wt * a.rows_in * WI;
+  const uint32_t lds_base = (uint32_t)(uintptr_t)(LDS_AS float4*)(lds4);
+
+  v16f acc[NACC];
+#pragma unroll
+  for (int q = 0; q < NACC; ++q) acc[q] = (v16f)(0.f);
+
+  for (int c0 = 0; c0 < a.rows_in; c0 += CC) {
+    const int ncc = min(CC, a.rows_in - c0);
+    __syncthreads();  // the previous pass is done with the LDS rows
+    stage_f32<NWAVE, ROWCAP>(lds4, in, a, blk, c0, ncc, t0);
+    __syncthreads();
+    for (int cl = 0; cl < ncc; ++cl) {
+      const int32_t* e = wav + (size_t)(c0 + cl) * WI;
+      // Table entries are wave-uniform; keep them in SGPRs.
+      const int ws = __builtin_amdgcn_readfirstlane(e[0]);
+      const uint32_t nl = (uint32_t)__builtin_amdgcn_readfirstlane(e[1]);
+      uint32_t o[4];
+      o[0] = (uint32_t)__builtin_amdgcn_readfirstlane(e[2]);
+      o[1] = (uint32_t)__builtin_amdgcn_readfirstlane(e[3]);
+      o[2] = WI > 4 ? (uint32_t)__builtin_amdgcn_readfirstlane(e[4]) : 0u;
+      o[3] = WI > 4 ? (uint32_t)__builtin_amdgcn_readfirstlane(e[5]) : 0u;
+      const float w = WEIGHTED ? __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                                               __builtin_bit_cast(int, a.w_in[c0 + cl])))
+                               : 0.f;
+      const uint32_t addr = lds_base + (uint32_t)((cl * ROWCAP + ws + lane * TP) * 4);
+      win_step<TP, DPW, NWIN, WEIGHTED>(acc, addr, o, nl, w);
+    }
+  }
+
+  // Epilogue: store the tile.
+  float* out = static_cast<float*>(a.out);
+  const int tl = t0 + lane * TP;
+#pragma unroll
+  for (int jj = 0; jj < DPW; ++jj) {
+    const int r = rt * DT + wave * DPW + jj;
+    if (r >= a.rows_out) break;
+    const float scale = (ADJ && a.w_out) ? a.w_out[r] : 1.f;
+    double gw = 0.0;
+    const float* xrow = nullptr;
+    if (ADJ && a.partial) xrow = a.x + (int64_t)beam * a.x_beam_stride + (int64_t)r * a.x_stride;
+    float* orow = out ? out + (int64_t)beam * a.out_beam_stride + (int64_t)r * a.out_stride : nullptr;
+#pragma unroll
+    for (int i4 = 0; i4 < TP / 4; ++i4) {
+      const int e0 = jj * TP + 4 * i4;
+      float4 v;
+      v.x = acc[(e0 + 0) / 16][(e0 + 0) % 16];
+      v.y = acc[(e0 + 1) / 16][(e0 + 1) % 16];
+      v.z = acc[(e0 + 2) / 16][(e0 + 2) % 16];
+      v.w = acc[(e0 + 3) / 16][(e0 + 3) % 16];
+      const int t = tl + 4 * i4;
+      if (ADJ && xrow) {
+        if (t + 4 <= a.nout) {
+          const float4 xv = *reinterpret_cast<const float4*>(xrow + t);
+          gw += (double)xv.x * (double)v.x;
+          gw += (double)xv.y * (double)v.y;
+          gw += (double)xv.z * (double)v.z;
+          gw += (double)xv.w * (double)v.w;
+        } else {
+          if (t + 0 < a.nout) gw += (double)xrow[t + 0] * (double)v.x;
+          if (t + 1 < a.nout) gw += (double)xrow[t + 1] * (double)v.y;
+          if (t + 2 < a.nout) gw += (double)xrow[t + 2] * (double)v.z;
+          if (t + 3 < a.nout) gw += (double)xrow[t + 3] * (double)v.w;
+        }
+      }
+      if (orow) {
+        if (ADJ) {
+          v.x *= scale;
+          v.y *= scale;
+          v.z *= scale;
+          v.w *= scale;
+        }
+        if (t + 4 <= a.nout) {
+          *reinterpret_cast<float4*>(orow + t) = v;
+        } else {
+          if (t + 0 < a.nout) orow[t + 0] = v.x;
+          if (t + 1 < a.nout) orow[t + 1] = v.y;
+          if (t + 2 < a.nout) orow[t + 2] = v.z;
+          if (t + 3 < a.nout) orow[t + 3] = v.w;
+        }
+      }
+    }
+    if (ADJ && xrow) {
+      // Fixed-order reduction over the 64 lanes of the wave.
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1) gw += __shfl_xor(gw, m, 64);
+      if (lane == 0) a.partial[((size_t)beam * a.n_time_tiles + tt) * a.rows_out + r] = gw;
+    }
+  }
+}
+
+template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, bool WEIGHTED, bool ADJ>
+__global__ __launch_bounds__(64 * NWAVE) void win_kernel(TileArgs a) {
+  __shared__ float4 lds4[CC * ROWCAP / 4];
+  const int nblk = a.n_time_tiles * a.n_row_tiles;
+  const int W = xcd_remap(blockIdx.x, nblk);
+  win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, WEIGHTED, ADJ>(a, W / a.n_row_tiles, W % a.n_row_tiles, blockIdx.y,
+                                                             lds4);
+}
+
+// Persistent form for batches of beams: blocks take tiles from a work table
+// (ordered by decreasing cost) through an atomic counter until it runs out.
+// Every beam shares the variant; per-beam pointers and tables come from its
+// descriptor.  The counter is cleared by a separate kernel before each launch.
+template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, bool WEIGHTED>
+__global__ __launch_bounds__(64 * NWAVE) void win_persistent(const BeamDesc* __restrict__ beams,
+                                                             const int32_t* __restrict__ order, int64_t ntiles,
+                                                             int* counter) {
+  __shared__ float4 lds4[CC * ROWCAP / 4];
+  __shared__ int s_tile;
+  for (;;) {
+    __syncthreads();  // everyone is done with s_tile and the LDS rows
+    if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
+    __syncthreads();
+    const int64_t k = s_tile;
+    if (k >= ntiles) break;
+    const int b = order[2 * k];
+    const int local = order[2 * k + 1];
+    const TileArgs& a = beams[b].a;
+    const int tt = local / a.n_row_tiles, rt = local % a.n_row_tiles;
+    win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, WEIGHTED, false>(a, tt, rt, 0, lds4);
+  }
+}
+
+__global__ void zero_counter_kernel(int* c) {
+  if (threadIdx.x == 0) c[0] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// uint8 -> int32 tile engine.  Lane l owns 4 consecutive samples in each of
+// Q groups spaced 256 samples apart, so its LDS reads of one group are
+// consecutive across lanes (no bank conflicts).  Per (input row, output row)
+// the lane reads the dword holding its 4 samples and the next one, aligns
+// them by the delay's byte offset and adds the 4 bytes into 4 int32
+// accumulators.  The output store is the dominant traffic, written with
+// non-temporal 16-byte stores.
+// ---------------------------------------------------------------------------
+template <int NWAVE, int ROWCAP>
+__device__ __forceinline__ void stage_u8(uint4* lds, const uint8_t* in, const TileArgs& a, const int32_t* blk, int c0,
+                                         int ncc, int t0) {
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  for (int cl = wave; cl < ncc; cl += NWAVE) {
+    const int sb = blk[2 * (c0 + cl)];
+    const int sl = blk[2 * (c0 + cl) + 1];
+    const uint8_t* src = in + (int64_t)(c0 + cl) * a.in_stride;
+    const int u0 = t0 + sb;
+    uint4* dst = lds + cl * (ROWCAP / 16);
+    const int nv = sl >> 4;
+#pragma unroll 2
+    for (int v = lane; v < nv; v += 64) {
+      const int u = u0 + 16 * v;
+      uint4 x;
+      if (u + 16 <= a.in_hi) {
+        x = *reinterpret_cast<const uint4*>(src + u);
+      } else {
+        uint32_t wv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          uint32_t acc = 0;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int uu = u + 4 * q + k;
+            const uint32_t byte = (uu < a.in_hi) ? (uint32_t)src[uu] : 0u;
+            acc |= byte << (8 * k);
+          }
+          wv[q] = acc;
+        }
+        x = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+      }
+      dst[v] = x;
+    }
+  }
+}
+
+template <int Q, int DPW, int NWAVE, int CC, int ROWCAP>
+__global__ __launch_bounds__(64 * NWAVE) void u8_kernel(TileArgs a) {
+  constexpr int ST = 256 * Q;
+  constexpr int DT = NWAVE * DPW;
+  constexpr int WI = DPW > 8 ? 8 : 4;
+  __shared__ uint4 lds[CC * ROWCAP / 16];
+  const int nblk = a.n_time_tiles * a.n_row_tiles;
+  const int W = xcd_remap(blockIdx.x, nblk);
+  const int tt = W / a.n_row_tiles, rt = W % a.n_row_tiles;
+  const int beam = blockIdx.y;
+  const int t0 = tt * ST;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  const int wt = rt * NWAVE + wave;
+  const uint8_t* in = static_cast<const uint8_t*>(a.in) + (int64_t)beam * a.in_beam_stride;
+  const int32_t* blk = a.blk + (size_t)rt * a.rows_in * 2;
+  const int32_t* wav = a.wav + (size_t)wt * a.rows_in * WI;
+  const uint32_t* lds32 = reinterpret_cast<const uint32_t*>(lds);
+
+  int acc[DPW][Q][4];
+#pragma unroll
+  for (int j = 0; j < DPW; ++j)
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[j][q][k] = 0;
+
+  for (int c0 = 0; c0 < a.rows_in; c0 += CC) {
+    const int ncc = min(CC, a.rows_in - c0);
+    __syncthreads();
+    stage_u8<NWAVE, ROWCAP>(lds, in, a, blk, c0, ncc, t0);
+    __syncthreads();
+    for (int cl = 0; cl < ncc; ++cl) {
+      const int32_t* e = wav + (size_t)(c0 + cl) * WI;
+      const uint32_t* row = lds32 + cl * (ROWCAP / 4);
+#pragma unroll
+      for (int jj = 0; jj < DPW; ++jj) {
+        const uint32_t o = ((uint32_t)e[jj >> 1] >> (16 * (jj & 1))) & 0xFFFFu;
+        const uint32_t sh = o & 3u;
+        const uint32_t* p = row + (o >> 2) + lane;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const uint32_t d0 = p[64 * q];
+          const uint32_t d1 = p[64 * q + 1];
+          const uint32_t v = __builtin_amdgcn_alignbyte(d1, d0, sh);
+          acc[jj][q][0] += (int)(v & 0xFFu);
+          acc[jj][q][1] += (int)((v >> 8) & 0xFFu);
+          acc[jj][q][2] += (int)((v >> 16) & 0xFFu);
+          acc[jj][q][3] += (int)(v >> 24);
+        }
+      }
+    }
+  }
+
+  int32_t* out = static_cast<int32_t*>(a.out) + (int64_t)beam * a.out_beam_stride;
+#pragma unroll
+  for (int jj = 0; jj < DPW; ++jj) {
+    const int r = rt * DT + wave * DPW + jj;
+    if (r >= a.rows_out) break;
+    int32_t* orow = out + (int64_t)r * a.out_stride;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int t = t0 + 4 * lane + 256 * q;
+      if (t + 4 <= a.nout) {
+        __builtin_nontemporal_store(acc[jj][q][0], orow + t + 0);
+        __builtin_nontemporal_store(acc[jj][q][1], orow + t + 1);
+        __builtin_nontemporal_store(acc[jj][q][2], orow + t + 2);
+        __builtin_nontemporal_store(acc[jj][q][3], orow + t + 3);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (t + k < a.nout) orow[t + k] = acc[jj][q][k];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Direct kernels: one work item per (output row, sample), one-dimensional
+// blocks along time, every term read straight from global memory.  This is
+// the paper's "generically tuned" form (Section 5: no DM-direction reuse) and
+// the fallback for plans whose delay spans fit no tiled variant.
+// ---------------------------------------------------------------------------
+template <bool WEIGHTED>
+__global__ __launch_bounds__(256) void direct_f32_kernel(const float* __restrict__ in, int64_t in_stride,
+                                                         int64_t in_beam_stride, const int32_t* __restrict__ delta,
+                                                         int nchan, const float* __restrict__ w, float* out,
+                                                         int64_t out_stride, int64_t out_beam_stride, int nsamp,
+                                                         int ntb) {
+  const int j = blockIdx.x / ntb;
+  const int t = (blockIdx.x - j * ntb) * 256 + threadIdx.x;
+  const int b = blockIdx.y;
+  if (t >= nsamp) return;
+  const int32_t* drow = delta + (size_t)j * nchan;
+  const float* src = in + (int64_t)b * in_beam_stride + t;
+  float acc = 0.f;
+  for (int c = 0; c < nchan; ++c) {
+    const float x = src[(int64_t)c * in_stride + drow[c]];
+    acc = WEIGHTED ? fmaf(w[c], x, acc) : acc + x;
+  }
+  out[(int64_t)b * out_beam_stride + (int64_t)j * out_stride + t] = acc;
+}
+
+__global__ __launch_bounds__(256) void direct_u8_kernel(const uint8_t* __restrict__ in, int64_t in_stride,
+                                                        int64_t in_beam_stride, const int32_t* __restrict__ delta,
+                                                        int nchan, int32_t* out, int64_t out_stride,
+                                                        int64_t out_beam_stride, int nsamp, int ntb) {
+  const int j = blockIdx.x / ntb;
+  const int t = (blockIdx.x - j * ntb) * 256 + threadIdx.x;
+  const int b = blockIdx.y;
+  if (t >= nsamp) return;
+  const int32_t* drow = delta + (size_t)j * nchan;
+  const uint8_t* src = in + (int64_t)b * in_beam_stride + t;
+  int32_t acc = 0;
+  for (int c = 0; c < nchan; ++c) acc += (int32_t)src[(int64_t)c * in_stride + drow[c]];
+  out[(int64_t)b * out_beam_stride + (int64_t)j * out_stride + t] = acc;
+}
+
+// Direct adjoint: one work item per (channel, input sample), summing over
+// DM trials in ascending order; block partial sums of x * G for grad_w.
+__global__ __launch_bounds__(256) void direct_adjoint_kernel(const float* __restrict__ g, int64_t g_stride,
+                                                             int64_t g_beam_stride, const int32_t* __restrict__ delta,
+                                                             int nchan, int ndm, int nsamp, int nin,
+                                                             const float* __restrict__ w, float* grad_in,
+                                                             int64_t gi_stride, int64_t gi_beam_stride,
+                                                             const float* __restrict__ x, int64_t x_stride,
+                                                             int64_t x_beam_stride, double* partial, int ntb) {
+  __shared__ double red[256];
+  const int c = blockIdx.x / ntb;
+  const int tb = blockIdx.x - c * ntb;
+  const int t = tb * 256 + threadIdx.x;
+  const int b = blockIdx.y;
+  float acc = 0.f;
+  if (t < nin) {
+    const float* gb = g + (int64_t)b * g_beam_stride;
+    for (int j = 0; j < ndm; ++j) {
+      const int s = t - delta[(size_t)j * nchan + c];
+      if (s >= 0 && s < nsamp) acc = acc + gb[(int64_t)j * g_stride + s];
+    }
+    if (grad_in) grad_in[(int64_t)b * gi_beam_stride + (int64_t)c * gi_stride + t] = (w ? w[c] : 1.f) * acc;
+  }
+  if (partial) {
+    double p = 0.0;
+    if (t < nin) p = (double)x[(int64_t)b * x_beam_stride + (int64_t)c * x_stride + t] * (double)acc;
+    red[threadIdx.x] = p;
+    __syncthreads();
+    for (int m = 128; m >= 1; m >>= 1) {
+      if ((int)threadIdx.x < m) red[threadIdx.x] += red[threadIdx.x + m];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[((size_t)b * ntb + tb) * nchan + c] = red[0];
+  }
+}
+
+// grad_w[c] = sum over parts p (ascending) of partial[p][c].
+__global__ __launch_bounds__(256) void reduce_gradw_kernel(const double* __restrict__ partial, int nparts, int nchan,
+                                                           float* grad_w) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= nchan) return;
+  double s = 0.0;
+  for (int p = 0; p < nparts; ++p) s += partial[(size_t)p * nchan + c];
+  grad_w[c] = (float)s;
+}
+
+// ---------------------------------------------------------------------------
+// Variant tables and launchers.
+// ---------------------------------------------------------------------------
+#define F32_VARIANTS(X)                            \
+  X(8, 8, 4, 64, 8, 1024)   /* 0: 32 DMs x 512  */ \
+  X(16, 8, 4, 72, 8, 2048)  /* 1: 32 DMs x 1024 */ \
+  X(8, 16, 4, 96, 8, 1024)  /* 2: 64 DMs x 512  */ \
+  X(16, 4, 4, 64, 8, 2048)  /* 3: 16 DMs x 1024 */ \
+  X(8, 4, 4, 48, 16, 1024)  /* 4: 16 DMs x 512  */ \
+  X(16, 8, 8, 72, 8, 2048)  /* 5: 64 DMs x 1024 */ \
+  X(8, 8, 8, 64, 8, 1024)   /* 6: 64 DMs x 512  */
+
+#define U8_VARIANTS(X)           \
+  X(4, 4, 4, 32, 2048) /* 0 */   \
+  X(4, 8, 4, 32, 2048) /* 1 */   \
+  X(2, 8, 4, 32, 1536) /* 2 */   \
+  X(4, 4, 8, 16, 2048) /* 3 */   \
+  X(2, 4, 4, 32, 1024) /* 4 */
+
+const std::vector<Variant>& variants_f32() {
+  static const std::vector<Variant> v = [] {
+    std::vector<Variant> r;
+#define MAKE_F32(TP, DPW, NW, NWIN, CC, RC)                                                        \
+  r.push_back(Variant{"win_tp" #TP "_dpw" #DPW "_nw" #NW, KIND_WIN_F32, TP, DPW, NW, NWIN, CC, RC});
+    F32_VARIANTS(MAKE_F32)
+#undef MAKE_F32
+    return r;
+  }();
+  return v;
+}
+
+const std::vector<Variant>& variants_u8() {
+  static const std::vector<Variant> v = [] {
+    std::vector<Variant> r;
+#define MAKE_U8(Q, DPW, NW, CC, RC) \
+  r.push_back(Variant{"u8_q" #Q "_dpw" #DPW "_nw" #NW, KIND_TILE_U8, Q, DPW, NW, 0, CC, RC});
+    U8_VARIANTS(MAKE_U8)
+#undef MAKE_U8
+    return r;
+  }();
+  return v;
+}
+
+hipError_t launch_tiled(const Variant& v, const TileArgs& a, int nbeam, bool adjoint, hipStream_t s) {
+  const int64_t nblk = (int64_t)a.n_time_tiles * a.n_row_tiles;
+  if (nblk < 1 || nblk > 0x7fffffff || nbeam < 1 || nbeam > 65535) return hipErrorInvalidConfiguration;
+  const dim3 grid((unsigned)nblk, (unsigned)nbeam);
+  const dim3 block(64 * v.nwave);
+  const bool weighted = adjoint ? false : (a.w_in != nullptr);
+  if (v.kind == KIND_WIN_F32) {
+#define LAUNCH_F32(TP, DPW, NW, NWIN, CC, RC)                                                                     \
+  if (v.tp == TP && v.dpw == DPW && v.nwave == NW && v.nwin == NWIN && v.cc == CC && v.rowcap == RC) {             \
+    if (adjoint)                                                                                                    \
+      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, false, true>), grid, block, 0, s, a);             \
+    else if (weighted)                                                                                              \
+      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, true, false>), grid, block, 0, s, a);             \
+    else                                                                                                            \
+      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, false, false>), grid, block, 0, s, a);            \
+    return hipGetLastError();                                                                                       \
+  }
+    F32_VARIANTS(LAUNCH_F32)
+#undef LAUNCH_F32
+  } else {
+#define LAUNCH_U8(Q, DPW, NW, CC, RC)                                                     \
+  if (v.tp == Q && v.dpw == DPW && v.nwave == NW && v.cc == CC && v.rowcap == RC) {       \
+    hipLaunchKernelGGL((u8_kernel<Q, DPW, NW, CC, RC>), grid, block, 0, s, a);            \
+    return hipGetLastError();                                                             \
+  }
+    U8_VARIANTS(LAUNCH_U8)
+#undef LAUNCH_U8
+  }
+  return hipErrorInvalidDeviceFunction;
+}
+
+hipError_t launch_batched(const Variant& v, const BeamDesc* d_beams, bool weighted, const int32_t* d_order,
+                          int64_t ntiles, int* d_counter, int grid, hipStream_t s) {
+  const dim3 block(64 * v.nwave);
+#define LAUNCH_P(TP, DPW, NW, NWIN, CC, RC)                                                                       \
+  if (v.tp == TP && v.dpw == DPW && v.nwave == NW && v.nwin == NWIN && v.cc == CC && v.rowcap == RC) {             \
+    if (weighted)                                                                                                   \
+      hipLaunchKernelGGL((win_persistent<TP, DPW, NW, NWIN, CC, RC, true>), dim3(grid), block, 0, s, d_beams,     \
+                         d_order, ntiles, d_counter);                                                              \
+    else                                                                                                            \
+      hipLaunchKernelGGL((win_persistent<TP, DPW, NW, NWIN, CC, RC, false>), dim3(grid), block, 0, s, d_beams,    \
+                         d_order, ntiles, d_counter);                                                              \
+    return hipGetLastError();                                                                                       \
+  }
+  if (v.kind == KIND_WIN_F32) {
+    F32_VARIANTS(LAUNCH_P)
+  }
+#undef LAUNCH_P
+  return hipErrorInvalidDeviceFunction;
+}
+
+int batched_blocks_per_cu(const Variant& v) {
+  int n = 0;
+#define OCC_P(TP, DPW, NW, NWIN, CC, RC)                                                                          \
+  if (v.tp == TP && v.dpw == DPW && v.nwave == NW && v.nwin == NWIN && v.cc == CC && v.rowcap == RC) {             \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, win_persistent<TP, DPW, NW, NWIN, CC, RC, false>,        \
+                                                     64 * NW, 0) != hipSuccess)                                    \
+      n = 1;                                                                                                        \
+    return n > 0 ? n : 1;                                                                                           \
+  }
+  if (v.kind == KIND_WIN_F32) {
+    F32_VARIANTS(OCC_P)
+  }
+#undef OCC_P
+  return 1;
+}
+
+hipError_t launch_zero_counter(int* d_counter, hipStream_t s) {
+  hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(64), 0, s, d_counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_direct_f32(const float* in, int64_t in_stride, int64_t in_beam_stride, const int32_t* delta,
+                             int nchan, int ndm, const float* w, float* out, int64_t out_stride,
+                             int64_t out_beam_stride, int nsamp, int nbeam, hipStream_t s) {
+  const int ntb = (nsamp + 255) / 256;
+  const int64_t gx = (int64_t)ntb * ndm;
+  if (gx > 0x7fffffff || nbeam > 65535) return hipErrorInvalidConfiguration;
+  if (w)
+    hipLaunchKernelGGL(direct_f32_kernel<true>, dim3((unsigned)gx, nbeam), dim3(256), 0, s, in, in_stride,
+                       in_beam_stride, delta, nchan, w, out, out_stride, out_beam_stride, nsamp, ntb);
+  else
+    hipLaunchKernelGGL(direct_f32_kernel<false>, dim3((unsigned)gx, nbeam), dim3(256), 0, s, in, in_stride,
+                       in_beam_stride, delta, nchan, w, out, out_stride, out_beam_stride, nsamp, ntb);
+  return hipGetLastError();
+}
+
+hipError_t launch_direct_u8(const uint8_t* in, int64_t in_stride, int64_t in_beam_stride, const int32_t* delta,
+                            int nchan, int ndm, int32_t* out, int64_t out_stride, int64_t out_beam_stride,
+                            int nsamp, int nbeam, hipStream_t s) {
+  const int ntb = (nsamp + 255) / 256;
+  const int64_t gx = (int64_t)ntb * ndm;
+  if (gx > 0x7fffffff || nbeam > 65535) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(direct_u8_kernel, dim3((unsigned)gx, nbeam), dim3(256), 0, s, in, in_stride, in_beam_stride,
+                     delta, nchan, out, out_stride, out_beam_stride, nsamp, ntb);
+  return hipGetLastError();
+}
+
+hipError_t launch_direct_adjoint(const float* g, int64_t g_stride, int64_t g_beam_stride, const int32_t* delta,
+                                 int nchan, int ndm, int nsamp, int nin, const float* w, float* grad_in,
+                                 int64_t gi_stride, int64_t gi_beam_stride, const float* x, int64_t x_stride,
+                                 int64_t x_beam_stride, double* partial, int nbeam, hipStream_t s) {
+  const int ntb = (nin + 255) / 256;
+  const int64_t gx = (int64_t)ntb * nchan;
+  if (gx > 0x7fffffff || nbeam > 65535) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(direct_adjoint_kernel, dim3((unsigned)gx, nbeam), dim3(256), 0, s, g, g_stride, g_beam_stride,
+                     delta, nchan, ndm, nsamp, nin, w, grad_in, gi_stride, gi_beam_stride, x, x_stride, x_beam_stride,
+                     partial, ntb);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_gradw(const double* partial, int nparts, int nchan, float* grad_w, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_gradw_kernel, dim3((nchan + 255) / 256), dim3(256), 0, s, partial, nparts, nchan, grad_w);
+  return hipGetLastError();
+}
+
+}  // namespace dd

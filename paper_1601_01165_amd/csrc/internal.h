@@ -1,0 +1,126 @@
+// Internal declarations shared by the host code and the kernels of the
+// dedispersion library.  Not part of the C-ABI (include/dedisp.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/dedisp.h"
+
+namespace dd {
+
+// ---------------------------------------------------------------------------
+// Kernel variants.  The paper tunes five parameters per platform and set-up
+// (Section 2.2): work-items per work-group in time and in DM, elements per
+// work-item in time and in DM, and local memory versus cache.  On gfx950 the
+// corresponding knobs are: samples per lane (tp), output rows per wave (dpw),
+// waves per block (nwave), the register window length (nwin), input rows
+// staged in LDS per pass (cc) and the LDS row capacity (rowcap); the direct
+// kernel is the "no local memory, no reuse" end of the space.
+// ---------------------------------------------------------------------------
+enum Kind { KIND_WIN_F32 = 0, KIND_TILE_U8 = 1 };
+
+struct Variant {
+  const char* name;
+  int kind;
+  int tp;      // f32: samples per lane; u8: dwords (4 samples each) per lane
+  int dpw;     // output rows per wave
+  int nwave;   // waves per block
+  int nwin;    // f32: window registers (0 for u8)
+  int cc;      // input rows per LDS pass
+  int rowcap;  // LDS row capacity (f32: elements, u8: bytes)
+  int st() const { return kind == KIND_WIN_F32 ? 64 * tp : 256 * tp; }
+  int dt() const { return nwave * dpw; }
+  int wav_ints() const { return kind == KIND_WIN_F32 ? (dpw > 8 ? 8 : 4) : (dpw > 8 ? 8 : 4); }
+};
+
+const std::vector<Variant>& variants_f32();
+const std::vector<Variant>& variants_u8();
+
+// Host-built tile tables for one variant on one delay matrix.
+//   blk[row_tile][rows_in]            {stage_base, stage_len}
+//   wav[wave_tile][rows_in][wav_ints] f32: {win_start, nl, packed u8 offsets...}
+//                                      u8:  {packed u16 offsets...}
+struct Tables {
+  int variant = -1;
+  int n_row_tiles = 0;
+  int n_wave_tiles = 0;
+  int max_stage = 0;
+  int32_t* d_blk = nullptr;
+  int32_t* d_wav = nullptr;
+  size_t bytes = 0;
+};
+
+// Arguments of the tiled kernels (passed by value).
+struct TileArgs {
+  const void* in;            // input rows of beam 0
+  int64_t in_stride;         // elements per input row
+  int64_t in_beam_stride;    // elements per beam
+  int in_shift;              // global index = virtual position + in_shift
+  int in_lo, in_hi;          // valid virtual positions [lo, hi); others read as 0
+  int rows_in;
+  int rows_out;
+  int nout;                  // output samples per row
+  int n_time_tiles;
+  int n_row_tiles;
+  const int32_t* blk;
+  const int32_t* wav;
+  const float* w_in;         // per input-row weight or null
+  void* out;
+  int64_t out_stride;
+  int64_t out_beam_stride;
+  const float* w_out;        // per output-row scale or null (adjoint: w[c])
+  // weight-gradient partials (adjoint only)
+  const float* x;            // forward input rows [beam][rows_out][x_stride] or null
+  int64_t x_stride;
+  int64_t x_beam_stride;
+  double* partial;           // [beam][n_time_tiles][rows_out]
+};
+
+// One beam of a batched launch.
+struct BeamDesc {
+  TileArgs a;                // in/out pointers already offset for the beam
+  int64_t tile_begin;        // first global tile index of this beam
+};
+
+// Launchers (engine.hip).  Each returns hipSuccess or the launch error.
+hipError_t launch_tiled(const Variant& v, const TileArgs& a, int nbeam, bool adjoint, hipStream_t s);
+hipError_t launch_direct_f32(const float* in, int64_t in_stride, int64_t in_beam_stride, const int32_t* delta,
+                             int nchan, int ndm, const float* w, float* out, int64_t out_stride,
+                             int64_t out_beam_stride, int nsamp, int nbeam, hipStream_t s);
+hipError_t launch_direct_u8(const uint8_t* in, int64_t in_stride, int64_t in_beam_stride, const int32_t* delta,
+                            int nchan, int ndm, int32_t* out, int64_t out_stride, int64_t out_beam_stride,
+                            int nsamp, int nbeam, hipStream_t s);
+hipError_t launch_direct_adjoint(const float* g, int64_t g_stride, int64_t g_beam_stride, const int32_t* delta,
+                                 int nchan, int ndm, int nsamp, int nin, const float* w, float* grad_in,
+                                 int64_t gi_stride, int64_t gi_beam_stride, const float* x, int64_t x_stride,
+                                 int64_t x_beam_stride, double* partial, int nbeam, hipStream_t s);
+hipError_t launch_reduce_gradw(const double* partial, int nparts, int nchan, float* grad_w, hipStream_t s);
+hipError_t launch_batched(const Variant& v, const BeamDesc* d_beams, bool weighted, const int32_t* d_order,
+                          int64_t ntiles, int* d_counter, int grid, hipStream_t s);
+hipError_t launch_zero_counter(int* d_counter, hipStream_t s);
+int batched_blocks_per_cu(const Variant& v);
+
+// Errors (plan.cpp).
+dedisp_status fail(dedisp_status st, const std::string& msg);
+dedisp_status hip_fail(hipError_t e, const char* what);
+
+}  // namespace dd
+
+// The plan object.
+struct dedisp_plan_s {
+  int device = 0;
+  int nchan = 0, ndm = 0, max_delay = 0;
+  double tsamp = 0;
+  std::vector<double> freq, dm;
+  std::vector<int32_t> delay;       // [ndm][nchan]
+  int32_t* d_delay = nullptr;       // device copy [ndm][nchan]
+  // adjoint view: out rows = channels, in rows = DMs, delay' = pad - delay
+  int adj_pad = 0;                  // max_delay rounded up to a multiple of 4
+  std::map<int, dd::Tables> fwd_f32, fwd_u8, adj_f32;
+  int var_f32 = -2, var_u8 = -2, var_adj = -2;  // -1 = direct kernel, -2 = not chosen yet
+};

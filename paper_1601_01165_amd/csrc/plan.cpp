@@ -1,0 +1,504 @@
+// Host side of the dedispersion library: plans, delay tables, tile tables,
+// argument validation and the forward / adjoint entry points of the C-ABI.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <functional>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace dd {
+
+static thread_local std::string g_last_error;
+
+dedisp_status fail(dedisp_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+dedisp_status hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return DEDISP_E_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// Delay table (Section 2, Equation 1; computed ahead of time, Section 2.1).
+//   f_h = highest channel frequency
+//   k   = 4150 * DM * (1/f^2 - 1/f_h^2) seconds, f in MHz
+//   delta = floor(k / tsamp + 1/2)
+// ---------------------------------------------------------------------------
+static dedisp_status build_delay_table(int nchan, const double* f, double tsamp, int ndm, const double* dm,
+                                       std::vector<int32_t>& out, int& max_delay) {
+  double fh = f[0];
+  for (int c = 0; c < nchan; ++c) {
+    if (!(f[c] > 0.0) || !std::isfinite(f[c])) return fail(DEDISP_E_INVALID, "channel frequency must be > 0 and finite");
+    fh = std::max(fh, f[c]);
+  }
+  const double inv_fh2 = 1.0 / (fh * fh);
+  out.assign((size_t)nchan * ndm, 0);
+  max_delay = 0;
+  for (int j = 0; j < ndm; ++j) {
+    if (!(dm[j] >= 0.0) || !std::isfinite(dm[j])) return fail(DEDISP_E_INVALID, "DM must be >= 0 and finite");
+    for (int c = 0; c < nchan; ++c) {
+      const double kdelay = 4150.0 * dm[j] * (1.0 / (f[c] * f[c]) - inv_fh2);
+      const double x = std::floor(kdelay / tsamp + 0.5);
+      if (!(x >= 0.0) || x > 2147483647.0) return fail(DEDISP_E_SHAPE, "a delay does not fit in int32");
+      out[(size_t)j * nchan + c] = (int32_t)x;
+      max_delay = std::max(max_delay, (int)x);
+    }
+  }
+  return DEDISP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tile tables.  `delay(r, c)` is the delay of output row r for input row c.
+// Output rows are grouped in block tiles of v.dt() rows and wave tiles of
+// v.dpw rows; rows past the end repeat the last row (their results are not
+// stored).
+// ---------------------------------------------------------------------------
+typedef std::function<int(int, int)> DelayFn;
+
+static bool build_tables(const Variant& v, int rows_out, int rows_in, const DelayFn& delay, std::vector<int32_t>& blk,
+                         std::vector<int32_t>& wav, int& n_row_tiles, int& max_stage, std::string& why) {
+  const int DT = v.dt(), DPW = v.dpw, NW = v.nwave, WI = v.wav_ints();
+  n_row_tiles = (rows_out + DT - 1) / DT;
+  const int n_wave_tiles = n_row_tiles * NW;
+  blk.assign((size_t)n_row_tiles * rows_in * 2, 0);
+  wav.assign((size_t)n_wave_tiles * rows_in * WI, 0);
+  max_stage = 0;
+  std::vector<int> d(DT);
+  for (int rt = 0; rt < n_row_tiles; ++rt) {
+    for (int c = 0; c < rows_in; ++c) {
+      for (int k = 0; k < DT; ++k) d[k] = delay(std::min(rt * DT + k, rows_out - 1), c);
+      if (v.kind == KIND_WIN_F32) {
+        const int bmin = *std::min_element(d.begin(), d.end());
+        const int sbase = bmin & ~3;
+        int need = 0;
+        for (int w = 0; w < NW; ++w) {
+          const int* dw = &d[w * DPW];
+          const int wmin = *std::min_element(dw, dw + DPW);
+          const int ws = (wmin - sbase) & ~3;
+          int maxo = 0;
+          int32_t* e = &wav[(((size_t)(rt * NW + w)) * rows_in + c) * WI];
+          for (int j = 0; j < DPW; ++j) {
+            const int o = dw[j] - sbase - ws;
+            if (o < 0 || o > v.nwin - v.tp) {
+              why = "delay span within a wave exceeds the register window";
+              return false;
+            }
+            maxo = std::max(maxo, o);
+            e[2 + j / 4] |= (int32_t)((uint32_t)o << (8 * (j % 4)));
+          }
+          const int nl = std::max(v.tp / 4 + 1, (v.tp + maxo + 3) / 4);
+          e[0] = ws;
+          e[1] = nl;
+          need = std::max(need, ws + 63 * v.tp + 4 * nl);
+        }
+        need = (need + 3) & ~3;
+        if (need > v.rowcap) {
+          why = "delay span within a block exceeds the LDS row";
+          return false;
+        }
+        blk[((size_t)rt * rows_in + c) * 2 + 0] = sbase;
+        blk[((size_t)rt * rows_in + c) * 2 + 1] = need;
+        max_stage = std::max(max_stage, need);
+      } else {
+        const int bmin = *std::min_element(d.begin(), d.end());
+        const int sbase = bmin & ~15;
+        int need = 0;
+        for (int w = 0; w < NW; ++w) {
+          const int* dw = &d[w * DPW];
+          int32_t* e = &wav[(((size_t)(rt * NW + w)) * rows_in + c) * WI];
+          for (int j = 0; j < DPW; ++j) {
+            const int o = dw[j] - sbase;
+            if (o < 0 || o > 65535) {
+              why = "delay span exceeds the 16-bit offset range";
+              return false;
+            }
+            e[j / 2] |= (int32_t)((uint32_t)o << (16 * (j % 2)));
+            need = std::max(need, (o & ~3) + 256 * v.tp + 4);
+          }
+        }
+        need = (need + 15) & ~15;
+        if (need > v.rowcap) {
+          why = "delay span within a block exceeds the LDS row";
+          return false;
+        }
+        blk[((size_t)rt * rows_in + c) * 2 + 0] = sbase;
+        blk[((size_t)rt * rows_in + c) * 2 + 1] = need;
+        max_stage = std::max(max_stage, need);
+      }
+    }
+  }
+  return true;
+}
+
+static void free_tables(Tables& t) {
+  if (t.d_blk) (void)hipFree(t.d_blk);
+  if (t.d_wav) (void)hipFree(t.d_wav);
+  t = Tables();
+}
+
+// Build and upload the tables of variant `vi` in direction `dir`
+// (0 = forward f32, 1 = forward u8, 2 = adjoint f32).
+dedisp_status ensure_tables(dedisp_plan p, int dir, int vi, Tables** out) {
+  std::map<int, Tables>& m = dir == 0 ? p->fwd_f32 : dir == 1 ? p->fwd_u8 : p->adj_f32;
+  auto it = m.find(vi);
+  if (it != m.end()) {
+    if (out) *out = &it->second;
+    return DEDISP_OK;
+  }
+  const std::vector<Variant>& vs = dir == 1 ? variants_u8() : variants_f32();
+  if (vi < 0 || vi >= (int)vs.size()) return fail(DEDISP_E_INVALID, "variant index out of range");
+  const Variant& v = vs[vi];
+  std::vector<int32_t> blk, wav;
+  int nrt = 0, maxs = 0;
+  std::string why;
+  bool ok;
+  const int C = p->nchan, D = p->ndm;
+  const int32_t* del = p->delay.data();
+  if (dir == 2) {
+    const int pad = p->adj_pad;
+    ok = build_tables(v, C, D, [&](int r, int c) { return pad - del[(size_t)c * C + r]; }, blk, wav, nrt, maxs, why);
+  } else {
+    ok = build_tables(v, D, C, [&](int r, int c) { return del[(size_t)r * C + c]; }, blk, wav, nrt, maxs, why);
+  }
+  if (!ok) return fail(DEDISP_E_UNTUNED, std::string(v.name) + ": " + why);
+  Tables t;
+  t.variant = vi;
+  t.n_row_tiles = nrt;
+  t.n_wave_tiles = nrt * v.nwave;
+  t.max_stage = maxs;
+  t.bytes = (blk.size() + wav.size()) * sizeof(int32_t);
+  hipError_t e = hipMalloc(&t.d_blk, blk.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&t.d_wav, wav.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMemcpy(t.d_blk, blk.data(), blk.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(t.d_wav, wav.data(), wav.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_tables(t);
+    return e == hipErrorOutOfMemory ? fail(DEDISP_E_NOMEM, "device allocation of tile tables failed")
+                                    : hip_fail(e, "uploading tile tables");
+  }
+  auto res = m.emplace(vi, t);
+  if (out) *out = &res.first->second;
+  return DEDISP_OK;
+}
+
+// Default variant choice: the first of a preference list whose tables build.
+static int default_variant(dedisp_plan p, int dir) {
+  static const int pref_f32[] = {1, 0, 3, 4};
+  static const int pref_u8[] = {0, 4, 1, 2};
+  const int* pref = dir == 1 ? pref_u8 : pref_f32;
+  const int n = 4;
+  for (int k = 0; k < n; ++k) {
+    if (ensure_tables(p, dir, pref[k], nullptr) == DEDISP_OK) return pref[k];
+  }
+  return -1;
+}
+
+static bool aligned16(const void* ptr) { return ((uintptr_t)ptr & 15u) == 0; }
+
+// The uint8 and adjoint kernels are chosen (and their tables built) on first
+// use or by dedisp_plan_prepare; -2 marks "not chosen yet".
+static void ensure_chosen(dedisp_plan p, int dir) {
+  int& v = dir == 0 ? p->var_f32 : dir == 1 ? p->var_u8 : p->var_adj;
+  if (v == -2) v = default_variant(p, dir);
+}
+
+}  // namespace dd
+
+using namespace dd;
+
+extern "C" {
+
+const char* dedisp_status_string(dedisp_status s) {
+  switch (s) {
+    case DEDISP_OK: return "ok";
+    case DEDISP_E_INVALID: return "invalid argument";
+    case DEDISP_E_SHAPE: return "invalid shape or stride";
+    case DEDISP_E_DTYPE: return "unsupported data type";
+    case DEDISP_E_ALIGN: return "misaligned pointer or row";
+    case DEDISP_E_NOMEM: return "out of memory";
+    case DEDISP_E_HIP: return "HIP runtime error";
+    case DEDISP_E_UNTUNED: return "no kernel variant fits";
+    case DEDISP_E_WORKSPACE: return "workspace too small";
+  }
+  return "unknown status";
+}
+
+const char* dedisp_last_error(void) { return g_last_error.c_str(); }
+
+dedisp_status dedisp_plan_create(dedisp_plan* plan, int32_t nchan, const double* freq_mhz, double tsamp_s,
+                                 int32_t ndm, const double* dm) {
+  if (!plan) return fail(DEDISP_E_INVALID, "plan pointer is NULL");
+  *plan = nullptr;
+  if (nchan < 1 || ndm < 1) return fail(DEDISP_E_INVALID, "nchan and ndm must be >= 1");
+  if (!freq_mhz || !dm) return fail(DEDISP_E_INVALID, "frequency or DM array is NULL");
+  if (!(tsamp_s > 0.0) || !std::isfinite(tsamp_s)) return fail(DEDISP_E_INVALID, "tsamp must be > 0 and finite");
+  dedisp_plan p = new (std::nothrow) dedisp_plan_s();
+  if (!p) return fail(DEDISP_E_NOMEM, "host allocation failed");
+  p->nchan = nchan;
+  p->ndm = ndm;
+  p->tsamp = tsamp_s;
+  p->freq.assign(freq_mhz, freq_mhz + nchan);
+  p->dm.assign(dm, dm + ndm);
+  dedisp_status st = build_delay_table(nchan, freq_mhz, tsamp_s, ndm, dm, p->delay, p->max_delay);
+  if (st != DEDISP_OK) {
+    delete p;
+    return st;
+  }
+  p->adj_pad = (p->max_delay + 3) & ~3;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess) e = hipMalloc(&p->d_delay, p->delay.size() * sizeof(int32_t));
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_delay, p->delay.data(), p->delay.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    st = hip_fail(e, "uploading the delay table");
+    dedisp_plan_destroy(p);
+    return st;
+  }
+  p->var_f32 = default_variant(p, 0);
+  *plan = p;
+  return DEDISP_OK;
+}
+
+dedisp_status dedisp_compute_delays(int32_t nchan, const double* freq_mhz, double tsamp_s, int32_t ndm,
+                                    const double* dm, int32_t* host, int32_t* max_delay) {
+  if (nchan < 1 || ndm < 1) return fail(DEDISP_E_INVALID, "nchan and ndm must be >= 1");
+  if (!freq_mhz || !dm || !host) return fail(DEDISP_E_INVALID, "an array pointer is NULL");
+  if (!(tsamp_s > 0.0) || !std::isfinite(tsamp_s)) return fail(DEDISP_E_INVALID, "tsamp must be > 0 and finite");
+  std::vector<int32_t> t;
+  int md = 0;
+  dedisp_status st = build_delay_table(nchan, freq_mhz, tsamp_s, ndm, dm, t, md);
+  if (st != DEDISP_OK) return st;
+  memcpy(host, t.data(), t.size() * sizeof(int32_t));
+  if (max_delay) *max_delay = md;
+  return DEDISP_OK;
+}
+
+dedisp_status dedisp_plan_destroy(dedisp_plan p) {
+  if (!p) return DEDISP_OK;
+  for (auto* m : {&p->fwd_f32, &p->fwd_u8, &p->adj_f32})
+    for (auto& kv : *m) free_tables(kv.second);
+  if (p->d_delay) (void)hipFree(p->d_delay);
+  delete p;
+  return DEDISP_OK;
+}
+
+dedisp_status dedisp_plan_info(dedisp_plan p, int32_t* nchan, int32_t* ndm, int32_t* max_delay) {
+  if (!p) return fail(DEDISP_E_INVALID, "plan is NULL");
+  if (nchan) *nchan = p->nchan;
+  if (ndm) *ndm = p->ndm;
+  if (max_delay) *max_delay = p->max_delay;
+  return DEDISP_OK;
+}
+
+dedisp_status dedisp_plan_delays(dedisp_plan p, int32_t* host) {
+  if (!p || !host) return fail(DEDISP_E_INVALID, "plan or output is NULL");
+  memcpy(host, p->delay.data(), p->delay.size() * sizeof(int32_t));
+  return DEDISP_OK;
+}
+
+int32_t dedisp_variant_count(dedisp_dtype t) {
+  return t == DEDISP_U8 ? (int32_t)variants_u8().size() : t == DEDISP_F32 ? (int32_t)variants_f32().size() : 0;
+}
+
+const char* dedisp_variant_name(dedisp_dtype t, int32_t i) {
+  if (t == DEDISP_U8 && i >= 0 && i < (int)variants_u8().size()) return variants_u8()[i].name;
+  if (t == DEDISP_F32 && i >= 0 && i < (int)variants_f32().size()) return variants_f32()[i].name;
+  return nullptr;
+}
+
+dedisp_status dedisp_plan_set_variant(dedisp_plan p, dedisp_dtype t, int32_t vi) {
+  if (!p) return fail(DEDISP_E_INVALID, "plan is NULL");
+  if (t != DEDISP_F32 && t != DEDISP_U8) return fail(DEDISP_E_DTYPE, "dtype must be F32 or U8");
+  const int dir = t == DEDISP_U8 ? 1 : 0;
+  if (vi >= 0) {
+    dedisp_status st = ensure_tables(p, dir, vi, nullptr);
+    if (st != DEDISP_OK) return st;
+  } else if (vi != -1) {
+    return fail(DEDISP_E_INVALID, "variant must be >= -1");
+  }
+  (t == DEDISP_U8 ? p->var_u8 : p->var_f32) = vi;
+  return DEDISP_OK;
+}
+
+int32_t dedisp_plan_variant(dedisp_plan p, dedisp_dtype t) {
+  if (!p) return -2;
+  ensure_chosen(p, t == DEDISP_U8 ? 1 : 0);
+  return t == DEDISP_U8 ? p->var_u8 : p->var_f32;
+}
+
+dedisp_status dedisp_plan_set_adjoint_variant(dedisp_plan p, int32_t vi) {
+  if (!p) return fail(DEDISP_E_INVALID, "plan is NULL");
+  if (vi >= 0) {
+    dedisp_status st = ensure_tables(p, 2, vi, nullptr);
+    if (st != DEDISP_OK) return st;
+  } else if (vi != -1) {
+    return fail(DEDISP_E_INVALID, "variant must be >= -1");
+  }
+  p->var_adj = vi;
+  return DEDISP_OK;
+}
+
+int32_t dedisp_plan_adjoint_variant(dedisp_plan p) {
+  if (!p) return -2;
+  ensure_chosen(p, 2);
+  return p->var_adj;
+}
+
+dedisp_status dedisp_plan_prepare(dedisp_plan p, dedisp_dtype t, int32_t adjoint) {
+  if (!p) return fail(DEDISP_E_INVALID, "plan is NULL");
+  if (t != DEDISP_F32 && t != DEDISP_U8) return fail(DEDISP_E_DTYPE, "dtype must be F32 or U8");
+  if (adjoint && t != DEDISP_F32) return fail(DEDISP_E_DTYPE, "the adjoint is float32 only");
+  const int dir = adjoint ? 2 : (t == DEDISP_U8 ? 1 : 0);
+  ensure_chosen(p, dir);
+  const int v = dir == 0 ? p->var_f32 : dir == 1 ? p->var_u8 : p->var_adj;
+  return v < 0 ? DEDISP_OK : ensure_tables(p, dir, v, nullptr);
+}
+
+dedisp_status dedisp_execute(dedisp_plan p, int32_t nbeam, int32_t nsamp, const void* d_in, dedisp_dtype in_type,
+                             int64_t in_stride, const float* d_w, void* d_out, dedisp_dtype out_type,
+                             int64_t out_stride, void* stream) {
+  if (!p) return fail(DEDISP_E_INVALID, "plan is NULL");
+  if (nbeam < 1 || nsamp < 1) return fail(DEDISP_E_INVALID, "nbeam and nsamp must be >= 1");
+  if (!d_in || !d_out) return fail(DEDISP_E_INVALID, "input or output pointer is NULL");
+  const bool f32 = in_type == DEDISP_F32 && out_type == DEDISP_F32;
+  const bool u8 = in_type == DEDISP_U8 && out_type == DEDISP_I32;
+  if (!f32 && !u8) return fail(DEDISP_E_DTYPE, "supported pairs: F32->F32, U8->I32");
+  if (u8 && d_w) return fail(DEDISP_E_DTYPE, "weights are not supported for uint8 input");
+  if (in_stride < (int64_t)nsamp + p->max_delay) return fail(DEDISP_E_SHAPE, "in_stride < nsamp + max_delay");
+  if (out_stride < nsamp) return fail(DEDISP_E_SHAPE, "out_stride < nsamp");
+  if (in_stride > 0x7fffffff - 64 || (int64_t)nsamp + p->max_delay > 0x7fffffff - 65536)
+    return fail(DEDISP_E_SHAPE, "rows longer than 2^31 samples are not supported");
+  const int esz = u8 ? 1 : 4;
+  if (!aligned16(d_in) || !aligned16(d_out) || (in_stride * esz) % 16 || (out_stride * 4) % 16 ||
+      (d_w && ((uintptr_t)d_w & 3)))
+    return fail(DEDISP_E_ALIGN, "pointers and row byte sizes must be multiples of 16 bytes");
+  hipStream_t s = (hipStream_t)stream;
+  ensure_chosen(p, u8 ? 1 : 0);
+  const int vi = u8 ? p->var_u8 : p->var_f32;
+  hipError_t e;
+  if (vi < 0) {
+    if (u8)
+      e = launch_direct_u8((const uint8_t*)d_in, in_stride, in_stride * p->nchan, p->d_delay, p->nchan, p->ndm,
+                           (int32_t*)d_out, out_stride, out_stride * p->ndm, nsamp, nbeam, s);
+    else
+      e = launch_direct_f32((const float*)d_in, in_stride, in_stride * p->nchan, p->d_delay, p->nchan, p->ndm, d_w,
+                            (float*)d_out, out_stride, out_stride * p->ndm, nsamp, nbeam, s);
+    return e == hipSuccess ? DEDISP_OK : hip_fail(e, "launching the direct kernel");
+  }
+  const int dir = u8 ? 1 : 0;
+  Tables* t = nullptr;
+  dedisp_status st = ensure_tables(p, dir, vi, &t);
+  if (st != DEDISP_OK) return st;
+  const Variant& v = (u8 ? variants_u8() : variants_f32())[vi];
+  TileArgs a = {};
+  a.in = d_in;
+  a.in_stride = in_stride;
+  a.in_beam_stride = in_stride * p->nchan;
+  a.in_shift = 0;
+  a.in_lo = 0;
+  a.in_hi = (int)in_stride;
+  a.rows_in = p->nchan;
+  a.rows_out = p->ndm;
+  a.nout = nsamp;
+  a.n_time_tiles = (nsamp + v.st() - 1) / v.st();
+  a.n_row_tiles = t->n_row_tiles;
+  a.blk = t->d_blk;
+  a.wav = t->d_wav;
+  a.w_in = d_w;
+  a.out = d_out;
+  a.out_stride = out_stride;
+  a.out_beam_stride = out_stride * p->ndm;
+  e = launch_tiled(v, a, nbeam, false, s);
+  return e == hipSuccess ? DEDISP_OK : hip_fail(e, "launching the tiled kernel");
+}
+
+size_t dedisp_adjoint_workspace_bytes(dedisp_plan p, int32_t nbeam, int32_t nin) {
+  if (!p || nbeam < 1 || nin < 1) return 0;
+  // Enough for the direct kernel (256-sample parts) and every tiled variant.
+  const int64_t parts = (int64_t)nbeam * ((nin + 255) / 256);
+  return (size_t)parts * p->nchan * sizeof(double);
+}
+
+dedisp_status dedisp_adjoint(dedisp_plan p, int32_t nbeam, int32_t nsamp, int32_t nin, const float* d_g,
+                             int64_t g_stride, const float* d_w, const float* d_in, int64_t in_stride,
+                             float* d_grad_in, int64_t gi_stride, float* d_grad_w, void* d_ws, size_t ws_bytes,
+                             void* stream) {
+  if (!p) return fail(DEDISP_E_INVALID, "plan is NULL");
+  if (nbeam < 1 || nsamp < 1 || nin < 1) return fail(DEDISP_E_INVALID, "nbeam, nsamp and nin must be >= 1");
+  if (!d_g) return fail(DEDISP_E_INVALID, "output gradient is NULL");
+  if (!d_grad_in && !d_grad_w) return DEDISP_OK;
+  if (d_grad_w && !d_in) return fail(DEDISP_E_INVALID, "grad_w needs the forward input");
+  if (g_stride < nsamp) return fail(DEDISP_E_SHAPE, "g_stride < nsamp");
+  if (d_grad_in && gi_stride < nin) return fail(DEDISP_E_SHAPE, "gi_stride < nin");
+  if (d_in && in_stride < nin) return fail(DEDISP_E_SHAPE, "in_stride < nin");
+  if ((int64_t)nsamp + p->max_delay > nin) return fail(DEDISP_E_SHAPE, "nin < nsamp + max_delay");
+  if (nin > 0x7fffffff - 65536) return fail(DEDISP_E_SHAPE, "rows longer than 2^31 samples are not supported");
+  if (!aligned16(d_g) || (g_stride * 4) % 16 || (d_grad_in && (!aligned16(d_grad_in) || (gi_stride * 4) % 16)) ||
+      (d_in && (!aligned16(d_in) || (in_stride * 4) % 16)) || (d_w && ((uintptr_t)d_w & 3)))
+    return fail(DEDISP_E_ALIGN, "pointers and row byte sizes must be multiples of 16 bytes");
+  if (d_grad_w) {
+    if (!d_ws) return fail(DEDISP_E_WORKSPACE, "workspace is NULL");
+    if (ws_bytes < dedisp_adjoint_workspace_bytes(p, nbeam, nin)) return fail(DEDISP_E_WORKSPACE, "workspace too small");
+    if ((uintptr_t)d_ws & 7) return fail(DEDISP_E_ALIGN, "workspace must be 8-byte aligned");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  double* partial = d_grad_w ? (double*)d_ws : nullptr;
+  hipError_t e;
+  int nparts;
+  ensure_chosen(p, 2);
+  const int vi = p->var_adj;
+  if (vi < 0) {
+    e = launch_direct_adjoint(d_g, g_stride, g_stride * p->ndm, p->d_delay, p->nchan, p->ndm, nsamp, nin, d_w,
+                              d_grad_in, gi_stride, gi_stride * p->nchan, d_in, in_stride, in_stride * p->nchan,
+                              partial, nbeam, s);
+    if (e != hipSuccess) return hip_fail(e, "launching the direct adjoint kernel");
+    nparts = nbeam * ((nin + 255) / 256);
+  } else {
+    Tables* t = nullptr;
+    dedisp_status st = ensure_tables(p, 2, vi, &t);
+    if (st != DEDISP_OK) return st;
+    const Variant& v = variants_f32()[vi];
+    TileArgs a = {};
+    a.in = d_g;
+    a.in_stride = g_stride;
+    a.in_beam_stride = g_stride * p->ndm;
+    a.in_shift = -p->adj_pad;
+    a.in_lo = p->adj_pad;
+    a.in_hi = p->adj_pad + nsamp;
+    a.rows_in = p->ndm;
+    a.rows_out = p->nchan;
+    a.nout = nin;
+    a.n_time_tiles = (nin + v.st() - 1) / v.st();
+    a.n_row_tiles = t->n_row_tiles;
+    a.blk = t->d_blk;
+    a.wav = t->d_wav;
+    a.w_in = nullptr;
+    a.out = d_grad_in;
+    a.out_stride = gi_stride;
+    a.out_beam_stride = gi_stride * p->nchan;
+    a.w_out = d_w;
+    a.x = d_in;
+    a.x_stride = in_stride;
+    a.x_beam_stride = in_stride * p->nchan;
+    a.partial = partial;
+    e = launch_tiled(v, a, nbeam, true, s);
+    if (e != hipSuccess) return hip_fail(e, "launching the tiled adjoint kernel");
+    nparts = nbeam * a.n_time_tiles;
+  }
+  if (d_grad_w) {
+    e = launch_reduce_gradw(partial, nparts, p->nchan, d_grad_w, s);
+    if (e != hipSuccess) return hip_fail(e, "launching the grad_w reduction");
+  }
+  return DEDISP_OK;
+}
+
+}  // extern "C"

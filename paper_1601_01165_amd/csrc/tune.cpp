@@ -1,0 +1,300 @@
+// Auto-tuning.  The paper tries every meaningful combination of its tuning
+// parameters and keeps the fastest, per platform, set-up and DM count
+// (Section 2.2, Section 3, Section 4.1).  Here the search runs over the
+// kernel variants compiled into the library (plus the direct kernel), timed
+// with HIP events on the plan's real delay tables, and the winner is kept in
+// the plan and in an optional JSON cache file.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace dd {
+dedisp_status ensure_tables(dedisp_plan p, int dir, int vi, Tables** out);
+
+// FNV-1a over the delay table: two plans with equal tables share tuning.
+static uint64_t table_hash(dedisp_plan p) {
+  uint64_t h = 1469598103934665603ull;
+  const unsigned char* b = reinterpret_cast<const unsigned char*>(p->delay.data());
+  const size_t n = p->delay.size() * sizeof(int32_t);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+static std::string device_name() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string s = prop.gcnArchName;
+  return s.substr(0, s.find(':'));
+}
+
+static std::string cache_key(dedisp_plan p, dedisp_dtype t, int nbeam, int nsamp) {
+  // Samples are bucketed by powers of two: tuning depends on the tile count,
+  // not on the exact length.
+  int bucket = 1;
+  while (bucket < nsamp) bucket <<= 1;
+  char buf[256];
+  snprintf(buf, sizeof(buf), "%s|%s|c%d|d%d|s%d|b%d|h%016llx", device_name().c_str(), t == DEDISP_U8 ? "u8" : "f32",
+           p->nchan, p->ndm, bucket, nbeam, (unsigned long long)table_hash(p));
+  return buf;
+}
+
+// Cache file: a JSON object, one entry per line:
+//   "key": {"variant": "name", "ms": 1.234},
+static bool cache_lookup(const char* path, const std::string& key, std::string& variant) {
+  if (!path) return false;
+  std::ifstream f(path);
+  if (!f) return false;
+  std::string line;
+  const std::string pat = "\"" + key + "\": {\"variant\": \"";
+  while (std::getline(f, line)) {
+    size_t k = line.find(pat);
+    if (k == std::string::npos) continue;
+    size_t s = k + pat.size();
+    size_t e = line.find('"', s);
+    if (e == std::string::npos) return false;
+    variant = line.substr(s, e - s);
+    return true;
+  }
+  return false;
+}
+
+static void cache_store(const char* path, const std::string& key, const std::string& variant, float ms) {
+  if (!path) return;
+  std::vector<std::string> entries;
+  {
+    std::ifstream f(path);
+    std::string line;
+    const std::string pat = "\"" + key + "\":";
+    while (f && std::getline(f, line)) {
+      if (line.find("\": {\"variant\"") == std::string::npos) continue;
+      if (line.find(pat) != std::string::npos) continue;
+      while (!line.empty() && (line.back() == ',' || line.back() == ' ')) line.pop_back();
+      entries.push_back(line);
+    }
+  }
+  char buf[512];
+  snprintf(buf, sizeof(buf), "  \"%s\": {\"variant\": \"%s\", \"ms\": %.6f}", key.c_str(), variant.c_str(), ms);
+  entries.push_back(buf);
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream f(tmp);
+    f << "{\n";
+    for (size_t i = 0; i < entries.size(); ++i) f << entries[i] << (i + 1 < entries.size() ? ",\n" : "\n");
+    f << "}\n";
+  }
+  (void)rename(tmp.c_str(), path);
+}
+
+// Median time in ms of `reps` launches of fn after one warm-up launch.
+template <typename F>
+static float time_ms(F fn, hipStream_t s, int reps, hipEvent_t e0, hipEvent_t e1) {
+  if (fn() != hipSuccess) return -1.f;
+  std::vector<float> t;
+  for (int r = 0; r < reps; ++r) {
+    if (hipEventRecord(e0, s) != hipSuccess) return -1.f;
+    if (fn() != hipSuccess) return -1.f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.f;
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.f;
+    t.push_back(ms);
+  }
+  std::sort(t.begin(), t.end());
+  return t[t.size() / 2];
+}
+
+// Last search of each plan and dtype: times per variant (-1 = does not fit),
+// the last entry being the direct kernel.
+static std::vector<float>& last_times(dedisp_plan p, dedisp_dtype t) {
+  static thread_local std::vector<std::pair<std::pair<dedisp_plan, int>, std::vector<float>>> store;
+  for (auto& kv : store)
+    if (kv.first.first == p && kv.first.second == (int)t) return kv.second;
+  store.push_back({{p, (int)t}, {}});
+  return store.back().second;
+}
+
+int autotune_batch_variant(const std::vector<dedisp_plan>& plans, const std::vector<int32_t>& nsamp,
+                           const std::vector<const float*>& d_in, const std::vector<int64_t>& in_stride,
+                           const std::vector<const float*>& d_w, const std::vector<float*>& d_out,
+                           const std::vector<int64_t>& out_stride) {
+  // Time each variant that fits every beam as one persistent launch over the
+  // real buffers (outputs are overwritten by the real run later).
+  const std::vector<Variant>& vs = variants_f32();
+  const int nb = (int)plans.size();
+  hipStream_t s;
+  hipEvent_t e0, e1;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return -1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  int best = -1;
+  float best_ms = 1e30f;
+  for (int vi = 0; vi < (int)vs.size(); ++vi) {
+    bool ok = true;
+    for (int i = 0; i < nb && ok; ++i) ok = ensure_tables(plans[i], 0, vi, nullptr) == DEDISP_OK;
+    if (!ok) continue;
+    dedisp_batch b = nullptr;
+    // Build a non-tuned batch pinned to this variant by temporarily making it
+    // the only fitting candidate is not possible through the C-ABI, so time
+    // the persistent kernel directly.
+    std::vector<BeamDesc> beams(nb);
+    std::vector<int32_t> order;
+    const Variant& v = vs[vi];
+    for (int i = 0; i < nb; ++i) {
+      Tables* t = nullptr;
+      ensure_tables(plans[i], 0, vi, &t);
+      TileArgs& a = beams[i].a;
+      a = TileArgs{};
+      a.in = d_in[i];
+      a.in_stride = in_stride[i];
+      a.in_hi = (int)in_stride[i];
+      a.rows_in = plans[i]->nchan;
+      a.rows_out = plans[i]->ndm;
+      a.nout = nsamp[i];
+      a.n_time_tiles = (nsamp[i] + v.st() - 1) / v.st();
+      a.n_row_tiles = t->n_row_tiles;
+      a.blk = t->d_blk;
+      a.wav = t->d_wav;
+      a.w_in = d_w[i];
+      a.out = d_out[i];
+      a.out_stride = out_stride[i];
+    }
+    std::vector<int> ord(nb);
+    for (int i = 0; i < nb; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return plans[x]->nchan > plans[y]->nchan; });
+    for (int i : ord) {
+      const int n = beams[i].a.n_time_tiles * beams[i].a.n_row_tiles;
+      for (int k = 0; k < n; ++k) {
+        order.push_back(i);
+        order.push_back(k);
+      }
+    }
+    (void)b;
+    BeamDesc* d_beams = nullptr;
+    int32_t* d_order = nullptr;
+    int* d_counter = nullptr;
+    hipError_t e = hipMalloc(&d_beams, sizeof(BeamDesc) * nb);
+    if (e == hipSuccess) e = hipMalloc(&d_order, sizeof(int32_t) * order.size());
+    if (e == hipSuccess) e = hipMalloc(&d_counter, 256);
+    if (e == hipSuccess) e = hipMemcpy(d_beams, beams.data(), sizeof(BeamDesc) * nb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+      int dev = 0, ncu = 0;
+      (void)hipGetDevice(&dev);
+      (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+      const int grid = ncu * batched_blocks_per_cu(v);
+      const int64_t ntiles = (int64_t)order.size() / 2;
+      const bool weighted = d_w[0] != nullptr;
+      float ms = time_ms(
+          [&]() {
+            hipError_t r = launch_zero_counter(d_counter, s);
+            return r == hipSuccess ? launch_batched(v, d_beams, weighted, d_order, ntiles, d_counter, grid, s) : r;
+          },
+          s, 2, e0, e1);
+      if (ms > 0 && ms < best_ms) {
+        best_ms = ms;
+        best = vi;
+      }
+    }
+    if (d_beams) (void)hipFree(d_beams);
+    if (d_order) (void)hipFree(d_order);
+    if (d_counter) (void)hipFree(d_counter);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  return best;
+}
+
+}  // namespace dd
+
+using namespace dd;
+
+extern "C" {
+
+dedisp_status dedisp_autotune(dedisp_plan p, int32_t nbeam, int32_t nsamp, dedisp_dtype t, const char* cache_path) {
+  if (!p) return fail(DEDISP_E_INVALID, "plan is NULL");
+  if (nbeam < 1 || nsamp < 1) return fail(DEDISP_E_INVALID, "nbeam and nsamp must be >= 1");
+  if (t != DEDISP_F32 && t != DEDISP_U8) return fail(DEDISP_E_DTYPE, "dtype must be F32 or U8");
+  const bool u8 = t == DEDISP_U8;
+  const std::vector<Variant>& vs = u8 ? variants_u8() : variants_f32();
+  const std::string key = cache_key(p, t, nbeam, nsamp);
+  std::string hit;
+  if (cache_lookup(cache_path, key, hit)) {
+    if (hit == "direct") return dedisp_plan_set_variant(p, t, -1);
+    for (int i = 0; i < (int)vs.size(); ++i)
+      if (hit == vs[i].name && dedisp_plan_set_variant(p, t, i) == DEDISP_OK) return DEDISP_OK;
+  }
+  const int esz = u8 ? 1 : 4;
+  const int64_t q = 16 / esz;
+  const int64_t in_stride = ((int64_t)nsamp + p->max_delay + q - 1) / q * q;
+  const int64_t out_stride = ((int64_t)nsamp + 3) / 4 * 4;
+  void* d_in = nullptr;
+  void* d_out = nullptr;
+  hipError_t e = hipMalloc(&d_in, (size_t)nbeam * p->nchan * in_stride * esz);
+  if (e == hipSuccess) e = hipMalloc(&d_out, (size_t)nbeam * p->ndm * out_stride * 4);
+  if (e == hipSuccess) e = hipMemset(d_in, 0, (size_t)nbeam * p->nchan * in_stride * esz);
+  if (e != hipSuccess) {
+    if (d_in) (void)hipFree(d_in);
+    return e == hipErrorOutOfMemory ? fail(DEDISP_E_NOMEM, "autotune scratch allocation failed")
+                                    : hip_fail(e, "autotune scratch");
+  }
+  hipStream_t s;
+  hipEvent_t e0, e1;
+  (void)hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const dedisp_dtype out_t = u8 ? DEDISP_I32 : DEDISP_F32;
+  std::vector<float>& times = last_times(p, t);
+  times.assign(vs.size() + 1, -1.f);
+  const int saved = u8 ? p->var_u8 : p->var_f32;
+  int best = -2;
+  float best_ms = 1e30f;
+  for (int vi = -1; vi < (int)vs.size(); ++vi) {
+    if (dedisp_plan_set_variant(p, t, vi) != DEDISP_OK) continue;
+    float ms = time_ms(
+        [&]() {
+          return dedisp_execute(p, nbeam, nsamp, d_in, t, in_stride, nullptr, d_out, out_t, out_stride, s) == DEDISP_OK
+                     ? hipSuccess
+                     : hipErrorUnknown;
+        },
+        s, 3, e0, e1);
+    times[vi < 0 ? vs.size() : (size_t)vi] = ms;
+    if (ms > 0 && ms < best_ms) {
+      best_ms = ms;
+      best = vi;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  (void)hipFree(d_in);
+  (void)hipFree(d_out);
+  if (best == -2) {
+    (void)dedisp_plan_set_variant(p, t, saved);
+    return fail(DEDISP_E_UNTUNED, "no variant ran");
+  }
+  dedisp_status st = dedisp_plan_set_variant(p, t, best);
+  if (st != DEDISP_OK) return st;
+  cache_store(cache_path, key, best < 0 ? "direct" : vs[best].name, best_ms);
+  return DEDISP_OK;
+}
+
+int32_t dedisp_autotune_times(dedisp_plan p, dedisp_dtype t, float* ms, int32_t n) {
+  if (!p || !ms) return 0;
+  std::vector<float>& times = last_times(p, t);
+  const int32_t k = std::min<int32_t>(n, (int32_t)times.size());
+  for (int32_t i = 0; i < k; ++i) ms[i] = times[i];
+  return k;
+}
+
+}  // extern "C"

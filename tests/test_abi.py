@@ -1,0 +1,119 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared entry
+point, and its host-side delay table equals the oracle's (two independent
+implementations of Section 2, Equation 1).  No GPU work is done here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(dedisp_[a-z_]+)\s*\(", text))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def clib():
+    from paper_1601_01165_amd import _clib
+
+    return _clib.load()
+
+
+def test_every_declared_symbol_is_exported(clib):
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(clib, n), n
+    from paper_1601_01165_amd import _clib
+
+    assert set(names) == set(_clib.SIGNATURES), "binding and header disagree"
+
+
+def test_status_strings(clib):
+    for s in range(9):
+        assert clib.dedisp_status_string(s)
+    assert clib.dedisp_status_string(99) == b"unknown status"
+
+
+def test_variant_names(clib):
+    import paper_1601_01165_amd as dd
+
+    f = dd.variant_names("f32")
+    u = dd.variant_names("u8")
+    assert len(f) >= 4 and len(u) >= 3
+    assert len(set(f)) == len(f) and len(set(u)) == len(u)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
+def test_host_delays_equal_oracle(k):
+    import paper_1601_01165_amd as dd
+
+    beams = synth.config(k)
+    seen = set()
+    for b in beams[:12]:
+        key = (b.nchan, b.ndm)
+        if key in seen:
+            continue
+        seen.add(key)
+        got = dd.compute_delays(b.freqs(), b.tsamp_s, b.dms())
+        ref = oracle.delay_table(b.freqs(), b.tsamp_s, b.dms())
+        assert np.array_equal(got, ref)
+
+
+def test_host_delays_any_order_and_duplicates():
+    import paper_1601_01165_amd as dd
+
+    rng = np.random.default_rng(3)
+    f = rng.uniform(300, 400, 37)
+    dms = np.concatenate([rng.uniform(0, 100, 20), [5.0, 5.0, 0.0]])
+    assert np.array_equal(dd.compute_delays(f, 1e-4, dms), oracle.delay_table(f, 1e-4, dms))
+
+
+def test_host_delays_errors(clib):
+    import paper_1601_01165_amd as dd
+    from paper_1601_01165_amd import _clib
+
+    cases = [
+        (([1400.0], 0.0, [1.0]), _clib.E_INVALID),
+        (([1400.0, -1.0], 1e-3, [1.0]), _clib.E_INVALID),
+        (([1400.0], 1e-3, [-1.0]), _clib.E_INVALID),
+        (([1400.0, float("nan")], 1e-3, [1.0]), _clib.E_INVALID),
+        (([1400.0], 1e-3, [float("inf")]), _clib.E_INVALID),
+        (([1.0, 1e9], 1e-9, [1e6]), _clib.E_SHAPE),
+    ]
+    for args, code in cases:
+        with pytest.raises(dd.DedispError) as ei:
+            dd.compute_delays(*args)
+        assert ei.value.status == code, args
+    out = np.empty(4, np.int32)
+    f = np.array([1.0, 2.0])
+    assert clib.dedisp_compute_delays(0, f.ctypes.data, 1.0, 1, f.ctypes.data, out.ctypes.data, None) == _clib.E_INVALID
+    assert clib.dedisp_compute_delays(2, None, 1.0, 1, f.ctypes.data, out.ctypes.data, None) == _clib.E_INVALID
+
+
+def test_null_handles_are_rejected(clib):
+    from paper_1601_01165_amd import _clib
+
+    assert clib.dedisp_plan_destroy(None) == _clib.OK
+    assert clib.dedisp_batch_destroy(None) == _clib.OK
+    assert clib.dedisp_plan_info(None, None, None, None) == _clib.E_INVALID
+    assert clib.dedisp_execute(None, 1, 1, None, 0, 1, None, None, 0, 1, None) == _clib.E_INVALID
+    assert clib.dedisp_adjoint(None, 1, 1, 1, None, 1, None, None, 0, None, 0, None, None, 0, None) == _clib.E_INVALID
+    assert clib.dedisp_execute_batched(None, None) == _clib.E_INVALID
+    assert clib.dedisp_plan_create(None, 1, None, 1.0, 1, None) == _clib.E_INVALID
+    h = ctypes.c_void_p()
+    f = np.array([1400.0])
+    assert clib.dedisp_plan_create(ctypes.byref(h), 0, f.ctypes.data, 1.0, 1, f.ctypes.data) == _clib.E_INVALID
+    assert not h.value

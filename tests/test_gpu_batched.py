@@ -1,0 +1,138 @@
+"""GPU checks of the batched (persistent, graph-captured) path: equal bit for
+bit to the per-beam launch loop, equal to the oracle, and deterministic
+across graph replays."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _dd():
+    import paper_1601_01165_amd as dd
+
+    return dd
+
+
+def _note(msg):
+    print(msg, flush=True)
+
+
+def _small_batch(nbeam=7, seed=31):
+    """Uneven beams in the band of the batched workload, scaled down."""
+    rng = np.random.default_rng(seed)
+    beams = []
+    for i in range(nbeam):
+        nc = int(rng.choice([64, 128, 256, 300]))
+        nd = int(rng.integers(20, 200))
+        ns = int(rng.integers(500, 3000))
+        beams.append(synth.Beam(nc, 1270.0, 1570.0, 50e-6, ns, nd, 0.25, "f32", seed * 100 + i, npulse=2))
+    return beams
+
+
+def _setup(beams, weighted=False):
+    dd = _dd()
+    plans, xs, outs, ref_in, deltas, ws = [], [], [], [], [], []
+    for b in beams:
+        delta = oracle.delay_table(b.freqs(), b.tsamp_s, b.dms())
+        nin = b.nsamp + int(delta.max())
+        x = synth.noise(b, nin)
+        for j, t0 in synth.pulses(b, int(delta.max())):
+            synth.inject(x, delta, j, t0, b.pulse_width, b.pulse_amp)
+        xg = dd.empty_rows(1, b.nchan, nin, torch.float32, "cuda")
+        xg.copy_(torch.from_numpy(x)[None])
+        plans.append(dd.Plan(b.freqs(), b.tsamp_s, b.dms()))
+        xs.append(xg)
+        outs.append(dd.empty_rows(1, b.ndm, b.nsamp, torch.float32, "cuda", zero=True))
+        ref_in.append(x)
+        deltas.append(delta)
+        if weighted:
+            ws.append(torch.from_numpy(np.random.default_rng(b.seed).uniform(0.5, 1.5, b.nchan).astype(np.float32))
+                      .cuda())
+    return plans, xs, outs, ref_in, deltas, (ws if weighted else None)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_batched_matches_per_beam_and_oracle(weighted):
+    dd = _dd()
+    beams = _small_batch()
+    plans, xs, outs, ref_in, deltas, ws = _setup(beams, weighted)
+    batch = dd.Batch(plans, xs, outs, weights=ws)
+    _note(f"batched execute weighted={weighted}")
+    batch.execute()
+    torch.cuda.synchronize()
+    got_b = [o.cpu().numpy().copy() for o in outs]
+    for o in outs:
+        o.zero_()
+    _note("per-beam loop")
+    batch.execute_per_beam()
+    torch.cuda.synchronize()
+    got_p = [o.cpu().numpy().copy() for o in outs]
+    for i, b in enumerate(beams):
+        assert np.array_equal(got_b[i], got_p[i]), f"beam {i}: batched != per-beam"
+        w = None if ws is None else ws[i].cpu().numpy()
+        ref = oracle.forward_f32(ref_in[i], deltas[i], b.nsamp, w)
+        assert np.array_equal(got_b[i], ref), f"beam {i}: batched != oracle"
+
+
+def test_graph_replay_deterministic():
+    dd = _dd()
+    beams = _small_batch(5, seed=37)
+    plans, xs, outs, ref_in, deltas, _ = _setup(beams)
+    batch = dd.Batch(plans, xs, outs)
+    results = []
+    for r in range(3):
+        _note(f"replay {r}")
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        batch.execute()
+        torch.cuda.synchronize()
+        results.append([o.cpu().numpy().copy() for o in outs])
+    for r in range(1, 3):
+        for i in range(len(beams)):
+            assert np.array_equal(results[0][i], results[r][i])
+    for i, b in enumerate(beams):
+        assert np.array_equal(results[0][i], oracle.forward_f32(ref_in[i], deltas[i], b.nsamp))
+
+
+def test_batched_tuned_matches():
+    dd = _dd()
+    beams = _small_batch(4, seed=41)
+    plans, xs, outs, ref_in, deltas, _ = _setup(beams)
+    batch = dd.Batch(plans, xs, outs, tune=True)
+    _note("tuned batch")
+    for o in outs:
+        o.zero_()
+    batch.execute()
+    torch.cuda.synchronize()
+    for i, b in enumerate(beams):
+        assert np.array_equal(outs[i].cpu().numpy(), oracle.forward_f32(ref_in[i], deltas[i], b.nsamp))
+
+
+def test_autotune_single_plan_and_cache(tmp_path):
+    dd = _dd()
+    b = synth.config(0)[0]
+    plan = dd.Plan(b.freqs(), b.tsamp_s, b.dms())
+    cache = str(tmp_path / "tune.json")
+    _note("autotune f32")
+    times = plan.autotune(1, b.nsamp, "f32", cache)
+    assert "direct" in times and any(v > 0 for v in times.values())
+    chosen = plan.variant("f32")
+    txt = open(cache).read()
+    assert "variant" in txt
+    plan2 = dd.Plan(b.freqs(), b.tsamp_s, b.dms())
+    plan2.autotune(1, b.nsamp, "f32", cache)  # cache hit
+    assert plan2.variant("f32") == chosen
+    # the tuned plan still matches the oracle
+    delta = oracle.delay_table(b.freqs(), b.tsamp_s, b.dms())
+    nin = b.nsamp + int(delta.max())
+    x = synth.noise(b, nin)
+    xg = dd.empty_rows(1, b.nchan, nin, torch.float32, "cuda")
+    xg.copy_(torch.from_numpy(x)[None])
+    out = dd.dedisperse(xg, plan2, nsamp=b.nsamp)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), oracle.forward_f32(x, delta, b.nsamp))
