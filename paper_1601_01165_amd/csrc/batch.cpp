@@ -61,8 +61,8 @@ static dedisp_status check_beam(int i, dedisp_plan p, int32_t ns, const float* i
   if (!in || !out) return fail(DEDISP_E_INVALID, at + "input or output pointer is NULL");
   if (is < (int64_t)ns + p->max_delay) return fail(DEDISP_E_SHAPE, at + "in_stride < nsamp + max_delay");
   if (os < ns) return fail(DEDISP_E_SHAPE, at + "out_stride < nsamp");
-  if (is > 0x7fffffff - 64 || (int64_t)ns + p->max_delay > 0x7fffffff - 65536)
-    return fail(DEDISP_E_SHAPE, at + "rows longer than 2^31 samples are not supported");
+  if (is > kMaxRow || (int64_t)ns + p->max_delay > kMaxRow)
+    return fail(DEDISP_E_SHAPE, at + "rows longer than 2^29 samples are not supported");
   if (((uintptr_t)in & 15) || ((uintptr_t)out & 15) || (is * 4) % 16 || (os * 4) % 16 || ((uintptr_t)w & 3))
     return fail(DEDISP_E_ALIGN, at + "pointers and row byte sizes must be multiples of 16 bytes");
   return DEDISP_OK;
@@ -169,7 +169,7 @@ dedisp_status dedisp_batch_create(dedisp_batch* out, int32_t nbeam, const dedisp
   int vi = -1;
   if (tune) vi = autotune_batch_variant(b->plans, b->nsamp, b->d_in, b->in_stride, b->d_w, b->d_out, b->out_stride);
   if (vi < 0) {
-    static const int pref[] = {1, 0, 3, 4, 5, 6, 2};
+    static const int pref[] = {0, 1, 2, 4, 3, 5};
     for (int k : pref) {
       bool ok = true;
       for (int i = 0; i < nbeam && ok; ++i) ok = ensure_tables(b->plans[i], 0, k, nullptr) == DEDISP_OK;

@@ -44,6 +44,54 @@ __device__ __forceinline__ int xcd_remap(int L, int N) {
 
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
+// A pointer the compiler must keep in SGPRs (its value is wave-uniform).
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+
+// Wave-uniform scalar loads (wait included) of a table entry and a weight.
+typedef int32_t ent2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ ent2_t sload_entry2(const int32_t* p) {
+  ent2_t r;
+  asm volatile("s_load_dwordx2 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(r) : "s"(p));
+  return r;
+}
+__device__ __forceinline__ ent4_t sload_entry4(const int32_t* p) {
+  ent4_t r;
+  asm volatile("s_load_dwordx4 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(r) : "s"(p));
+  return r;
+}
+__device__ __forceinline__ ent8_t sload_entry8(const int32_t* p) {
+  ent8_t r;
+  asm volatile("s_load_dwordx8 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(r) : "s"(p));
+  return r;
+}
+template <typename E>
+__device__ __forceinline__ E sload_entry_t(const int32_t* p);
+template <>
+__device__ __forceinline__ ent4_t sload_entry_t<ent4_t>(const int32_t* p) {
+  return sload_entry4(p);
+}
+template <>
+__device__ __forceinline__ ent8_t sload_entry_t<ent8_t>(const int32_t* p) {
+  return sload_entry8(p);
+}
+template <>
+__device__ __forceinline__ ent16_t sload_entry_t<ent16_t>(const int32_t* p) {
+  ent16_t r;
+  asm volatile("s_load_dwordx16 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(r) : "s"(p));
+  return r;
+}
+__device__ __forceinline__ float sload_f32(const float* p) {
+  float r;
+  asm volatile("s_load_dword %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(r) : "s"(p));
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // FP32 tile engine with the register window.
 // ---------------------------------------------------------------------------
@@ -77,44 +125,112 @@ __device__ __forceinline__ void stage_f32(float4* lds4, const float* in, const T
   }
 }
 
-template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, bool WEIGHTED, bool ADJ>
+// Asynchronous form: 16-byte buffer loads that write LDS directly (no VGPR
+// round trip), completed by `s_waitcnt vmcnt(0)`.  Each row gets a buffer
+// resource covering its valid range, so positions outside it read as zero
+// without a branch (the adjoint relies on this for its virtual padding).
+template <int NWAVE, int ROWCAP>
+__device__ __forceinline__ void stage_f32_async(float4* lds4, const float* in, const TileArgs& a,
+                                                const int32_t* blk, int c0, int ncc, int t0) {
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  for (int cl = wave; cl < ncc; cl += NWAVE) {
+    const ent2_t bl = sload_entry2(blk + 2 * (c0 + cl));
+    const int sb = bl[0];
+    const int sl = bl[1];
+    const float* base = in + (int64_t)(c0 + cl) * a.in_stride + a.in_lo + a.in_shift;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (a.in_hi - a.in_lo) * 4, 0x00020000);
+    const int u0 = t0 + sb - a.in_lo;
+    const int nv = sl >> 2;
+    for (int v0 = 0; v0 < nv; v0 += 64) {
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (LDS_AS void*)(lds4 + cl * (ROWCAP / 4) + v0), 16,
+                                               (u0 + 4 * (v0 + lane)) * 4, 0, 0, 0);
+    }
+  }
+}
+
+// After the asynchronous loads of a pass have landed: rewrite the one 16-byte
+// chunk per row that straddles the end of the valid range (valid elements
+// from memory, the rest zero), whatever the hardware returned for it.  Only
+// the adjoint's range can end off a 16-byte boundary.
+template <int NWAVE, int ROWCAP>
+__device__ __forceinline__ void fix_tail_async(float4* lds4, const float* in, const TileArgs& a,
+                                               const int32_t* blk, int c0, int ncc, int t0) {
+  if ((a.in_hi & 3) == 0) return;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  const int hi4 = a.in_hi & ~3;
+  for (int cl = wave; cl < ncc; cl += NWAVE) {
+    const ent2_t bl = sload_entry2(blk + 2 * (c0 + cl));
+    const int v = (hi4 - (t0 + bl[0])) >> 2;
+    if (lane == 0 && v >= 0 && 4 * v < bl[1]) {
+      const float* src = in + (int64_t)(c0 + cl) * a.in_stride + a.in_shift;
+      float4 x;
+      x.x = src[hi4];
+      x.y = (hi4 + 1 < a.in_hi) ? src[hi4 + 1] : 0.f;
+      x.z = (hi4 + 2 < a.in_hi) ? src[hi4 + 2] : 0.f;
+      x.w = 0.f;
+      lds4[cl * (ROWCAP / 4) + v] = x;
+    }
+  }
+}
+
+// NBUF = 1: synchronous staging through registers, one LDS buffer.
+// NBUF = 2: asynchronous LDS loads into two buffers; the rows of pass p + 1
+// are in flight while pass p is summed.
+template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool WEIGHTED, bool ADJ>
 __device__ __forceinline__ void win_tile(const TileArgs& a, int tt, int rt, int beam, float4* lds4) {
   constexpr int ST = 64 * TP;
   constexpr int DT = NWAVE * DPW;
   constexpr int NACC = TP * DPW / 16;
-  constexpr int WI = DPW > 8 ? 8 : 4;
+  constexpr int WI = EntT<DPW>::ints;
   const int t0 = tt * ST;
   const int wave = wave_id(), lane = threadIdx.x & 63;
   const int wt = rt * NWAVE + wave;
   const float* in = static_cast<const float*>(a.in) + (int64_t)beam * a.in_beam_stride;
-  const int32_t* __restrict__ blk = a.blk + (size_t)rt * a.rows_in * 2;
-  const int32_t* __restrict__ wav = a.wav + (size_t)wt * a.rows_in * WI;
+  const int32_t* __restrict__ blk = uniform_ptr(a.blk + (size_t)rt * a.rows_in * 2);
+  const int32_t* __restrict__ wav = uniform_ptr(a.wav + (size_t)wt * a.rows_in * WI);
+  const float* w_in = WEIGHTED ? uniform_ptr(a.w_in) : nullptr;
   const uint32_t lds_base = (uint32_t)(uintptr_t)(LDS_AS float4*)(lds4);
 
   v16f acc[NACC];
 #pragma unroll
   for (int q = 0; q < NACC; ++q) acc[q] = (v16f)(0.f);
 
-  for (int c0 = 0; c0 < a.rows_in; c0 += CC) {
+  // The wave's table entry (and weight) of the current input row live in
+  // SGPRs; each step fetches the next row's with scalar loads.
+  typedef typename EntT<DPW>::type E;
+  E cur = sload_entry_t<E>(wav);
+  float wcur = WEIGHTED ? sload_f32(w_in) : 0.f;
+  const int npass = (a.rows_in + CC - 1) / CC;
+  if (NBUF == 2) {
+    __syncthreads();  // a previous tile of this block is done with the LDS rows
+    stage_f32_async<NWAVE, ROWCAP>(lds4, in, a, blk, 0, min(CC, a.rows_in), t0);
+  }
+  for (int p = 0; p < npass; ++p) {
+    const int c0 = p * CC;
     const int ncc = min(CC, a.rows_in - c0);
-    __syncthreads();  // the previous pass is done with the LDS rows
-    stage_f32<NWAVE, ROWCAP>(lds4, in, a, blk, c0, ncc, t0);
-    __syncthreads();
+    const int bufrow = NBUF == 2 ? (p & 1) * CC : 0;
+    if (NBUF == 1) {
+      __syncthreads();  // the previous pass is done with the LDS rows
+      stage_f32<NWAVE, ROWCAP>(lds4, in, a, blk, c0, ncc, t0);
+      __syncthreads();
+    } else {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's rows of pass p have landed
+      fix_tail_async<NWAVE, ROWCAP>(lds4 + (p & 1) * CC * (ROWCAP / 4), in, a, blk, c0, ncc, t0);
+      __syncthreads();  // every wave's have; every wave is done with pass p - 1
+      if (p + 1 < npass)
+        stage_f32_async<NWAVE, ROWCAP>(lds4 + ((p + 1) & 1) * CC * (ROWCAP / 4), in, a, blk, c0 + CC,
+                                       min(CC, a.rows_in - c0 - CC), t0);
+    }
     for (int cl = 0; cl < ncc; ++cl) {
-      const int32_t* e = wav + (size_t)(c0 + cl) * WI;
-      // Table entries are wave-uniform; keep them in SGPRs.
-      const int ws = __builtin_amdgcn_readfirstlane(e[0]);
-      const uint32_t nl = (uint32_t)__builtin_amdgcn_readfirstlane(e[1]);
-      uint32_t o[4];
-      o[0] = (uint32_t)__builtin_amdgcn_readfirstlane(e[2]);
-      o[1] = (uint32_t)__builtin_amdgcn_readfirstlane(e[3]);
-      o[2] = WI > 4 ? (uint32_t)__builtin_amdgcn_readfirstlane(e[4]) : 0u;
-      o[3] = WI > 4 ? (uint32_t)__builtin_amdgcn_readfirstlane(e[5]) : 0u;
-      const float w = WEIGHTED ? __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
-                                                               __builtin_bit_cast(int, a.w_in[c0 + cl])))
-                               : 0.f;
-      const uint32_t addr = lds_base + (uint32_t)((cl * ROWCAP + ws + lane * TP) * 4);
-      win_step<TP, DPW, NWIN, WEIGHTED>(acc, addr, o, nl, w);
+      const int cn = min(c0 + cl + 1, a.rows_in - 1);
+      const uint32_t addr = lds_base + (uint32_t)(((bufrow + cl) * ROWCAP + cur[0] + lane * TP) * 4);
+      E nxt;
+      float wn = 0.f;
+      win_step<TP, DPW, NWIN, WEIGHTED>(acc, addr, cur, wav + (size_t)cn * WI, nxt, wcur,
+                                        WEIGHTED ? w_in + cn : nullptr, wn);
+      cur = nxt;
+      wcur = wn;
     }
   }
 
@@ -179,24 +295,24 @@ __device__ __forceinline__ void win_tile(const TileArgs& a, int tt, int rt, int 
   }
 }
 
-template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, bool WEIGHTED, bool ADJ>
+template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool WEIGHTED, bool ADJ>
 __global__ __launch_bounds__(64 * NWAVE) void win_kernel(TileArgs a) {
-  __shared__ float4 lds4[CC * ROWCAP / 4];
+  __shared__ float4 lds4[NBUF * CC * ROWCAP / 4];
   const int nblk = a.n_time_tiles * a.n_row_tiles;
   const int W = xcd_remap(blockIdx.x, nblk);
-  win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, WEIGHTED, ADJ>(a, W / a.n_row_tiles, W % a.n_row_tiles, blockIdx.y,
-                                                             lds4);
+  win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, WEIGHTED, ADJ>(a, W / a.n_row_tiles, W % a.n_row_tiles,
+                                                                   blockIdx.y, lds4);
 }
 
 // Persistent form for batches of beams: blocks take tiles from a work table
 // (ordered by decreasing cost) through an atomic counter until it runs out.
 // Every beam shares the variant; per-beam pointers and tables come from its
 // descriptor.  The counter is cleared by a separate kernel before each launch.
-template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, bool WEIGHTED>
+template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool WEIGHTED>
 __global__ __launch_bounds__(64 * NWAVE) void win_persistent(const BeamDesc* __restrict__ beams,
                                                              const int32_t* __restrict__ order, int64_t ntiles,
                                                              int* counter) {
-  __shared__ float4 lds4[CC * ROWCAP / 4];
+  __shared__ float4 lds4[NBUF * CC * ROWCAP / 4];
   __shared__ int s_tile;
   for (;;) {
     __syncthreads();  // everyone is done with s_tile and the LDS rows
@@ -208,7 +324,7 @@ __global__ __launch_bounds__(64 * NWAVE) void win_persistent(const BeamDesc* __r
     const int local = order[2 * k + 1];
     const TileArgs& a = beams[b].a;
     const int tt = local / a.n_row_tiles, rt = local % a.n_row_tiles;
-    win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, WEIGHTED, false>(a, tt, rt, 0, lds4);
+    win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, WEIGHTED, false>(a, tt, rt, 0, lds4);
   }
 }
 
@@ -266,7 +382,8 @@ template <int Q, int DPW, int NWAVE, int CC, int ROWCAP>
 __global__ __launch_bounds__(64 * NWAVE) void u8_kernel(TileArgs a) {
   constexpr int ST = 256 * Q;
   constexpr int DT = NWAVE * DPW;
-  constexpr int WI = DPW > 8 ? 8 : 4;
+  constexpr int WI = 4;  // packed 16-bit offsets, DPW <= 8
+  static_assert(DPW <= 8, "uint8 variants pack at most 8 offsets");
   __shared__ uint4 lds[CC * ROWCAP / 16];
   const int nblk = a.n_time_tiles * a.n_row_tiles;
   const int W = xcd_remap(blockIdx.x, nblk);
@@ -277,8 +394,9 @@ __global__ __launch_bounds__(64 * NWAVE) void u8_kernel(TileArgs a) {
   const int wt = rt * NWAVE + wave;
   const uint8_t* in = static_cast<const uint8_t*>(a.in) + (int64_t)beam * a.in_beam_stride;
   const int32_t* blk = a.blk + (size_t)rt * a.rows_in * 2;
-  const int32_t* wav = a.wav + (size_t)wt * a.rows_in * WI;
+  const int32_t* __restrict__ wav = uniform_ptr(a.wav + (size_t)wt * a.rows_in * WI);
   const uint32_t* lds32 = reinterpret_cast<const uint32_t*>(lds);
+  typedef ent4_t E;
 
   int acc[DPW][Q][4];
 #pragma unroll
@@ -288,17 +406,27 @@ __global__ __launch_bounds__(64 * NWAVE) void u8_kernel(TileArgs a) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) acc[j][q][k] = 0;
 
+  // The wave's offsets for the rows of a pass are copied into LDS with the
+  // rows; each step reads the next row's entry (a broadcast LDS read) one
+  // step ahead of its use.
+  static_assert(WI == 4, "uint8 variants use 4-int table entries");
+  __shared__ E tab[NWAVE][CC];
   for (int c0 = 0; c0 < a.rows_in; c0 += CC) {
     const int ncc = min(CC, a.rows_in - c0);
     __syncthreads();
     stage_u8<NWAVE, ROWCAP>(lds, in, a, blk, c0, ncc, t0);
+    if (lane < ncc) tab[wave][lane] = *reinterpret_cast<const E*>(wav + (size_t)(c0 + lane) * WI);
     __syncthreads();
+    E cur = tab[wave][0];
     for (int cl = 0; cl < ncc; ++cl) {
-      const int32_t* e = wav + (size_t)(c0 + cl) * WI;
+      const E nxt = tab[wave][min(cl + 1, ncc - 1)];
       const uint32_t* row = lds32 + cl * (ROWCAP / 4);
+      uint32_t cw[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) cw[k] = (uint32_t)__builtin_amdgcn_readfirstlane(cur[k]);
 #pragma unroll
       for (int jj = 0; jj < DPW; ++jj) {
-        const uint32_t o = ((uint32_t)e[jj >> 1] >> (16 * (jj & 1))) & 0xFFFFu;
+        const uint32_t o = (cw[jj >> 1] >> (16 * (jj & 1))) & 0xFFFFu;
         const uint32_t sh = o & 3u;
         const uint32_t* p = row + (o >> 2) + lane;
 #pragma unroll
@@ -312,6 +440,7 @@ __global__ __launch_bounds__(64 * NWAVE) void u8_kernel(TileArgs a) {
           acc[jj][q][3] += (int)(v >> 24);
         }
       }
+      cur = nxt;
     }
   }
 
@@ -428,27 +557,42 @@ __global__ __launch_bounds__(256) void reduce_gradw_kernel(const double* __restr
 // ---------------------------------------------------------------------------
 // Variant tables and launchers.
 // ---------------------------------------------------------------------------
-#define F32_VARIANTS(X)                            \
-  X(8, 8, 4, 64, 8, 1024)   /* 0: 32 DMs x 512  */ \
-  X(16, 8, 4, 72, 8, 2048)  /* 1: 32 DMs x 1024 */ \
-  X(8, 16, 4, 96, 8, 1024)  /* 2: 64 DMs x 512  */ \
-  X(16, 4, 4, 64, 8, 2048)  /* 3: 16 DMs x 1024 */ \
-  X(8, 4, 4, 48, 16, 1024)  /* 4: 16 DMs x 512  */ \
-  X(16, 8, 8, 72, 8, 2048)  /* 5: 64 DMs x 1024 */ \
-  X(8, 8, 8, 64, 8, 1024)   /* 6: 64 DMs x 512  */
+// (index, TP samples per lane, DPW rows per wave, NWAVE, NWIN window registers,
+//  CC rows per LDS pass, ROWCAP floats per LDS row, NBUF LDS buffers)
+// A lane owns TP consecutive samples; TP/4 odd (12, 20) keeps its 16-byte LDS
+// reads free of bank conflicts.
+#define F32_VARIANTS(X)                                          \
+  X(0, 12, 4, 4, 36, 8, 1024, 1)   /* 16 DMs x 768             */ \
+  X(1, 12, 4, 4, 48, 8, 1024, 1)   /* 16 DMs x 768, wide spans */ \
+  X(2, 8, 8, 4, 64, 8, 1024, 1)    /* 32 DMs x 512             */ \
+  X(3, 16, 8, 4, 72, 8, 2048, 1)   /* 32 DMs x 1024            */ \
+  X(4, 8, 4, 4, 48, 16, 1024, 1)   /* 16 DMs x 512             */ \
+  X(5, 16, 4, 4, 64, 8, 2048, 1)   /* 16 DMs x 1024            */ \
+  X(6, 12, 4, 4, 36, 4, 1024, 2)   /* 16 DMs x 768, async      */ \
+  X(7, 12, 8, 4, 56, 4, 1024, 2)   /* 32 DMs x 768, async      */ \
+  X(8, 20, 4, 4, 44, 4, 1536, 2)   /* 16 DMs x 1280, async     */ \
+  X(9, 12, 4, 8, 36, 4, 1024, 2)   /* 32 DMs x 768, async      */ \
+  X(10, 12, 8, 8, 56, 4, 1280, 2)  /* 64 DMs x 768, async      */ \
+  X(11, 12, 4, 4, 48, 4, 1024, 2)  /* 16 DMs x 768, async      */ \
+  X(12, 8, 8, 4, 64, 4, 1024, 2)   /* 32 DMs x 512, async      */
 
-#define U8_VARIANTS(X)           \
-  X(4, 4, 4, 32, 2048) /* 0 */   \
-  X(4, 8, 4, 32, 2048) /* 1 */   \
-  X(2, 8, 4, 32, 1536) /* 2 */   \
-  X(4, 4, 8, 16, 2048) /* 3 */   \
-  X(2, 4, 4, 32, 1024) /* 4 */
+// (index, Q dwords per lane, DPW, NWAVE, CC rows per LDS pass, ROWCAP bytes)
+#define U8_VARIANTS(X)                            \
+  X(0, 4, 4, 4, 16, 2048) /* 16 DMs x 1024 */     \
+  X(1, 4, 2, 4, 32, 1536) /*  8 DMs x 1024 */     \
+  X(2, 2, 4, 4, 16, 1536) /* 16 DMs x 512  */     \
+  X(3, 4, 4, 4, 32, 2048) /* 16 DMs x 1024 */     \
+  X(4, 2, 2, 4, 32, 1024) /*  8 DMs x 512  */     \
+  X(5, 4, 8, 4, 16, 4096) /* 32 DMs x 1024 */     \
+  X(6, 4, 4, 8, 16, 4096) /* 32 DMs x 1024 */
 
 const std::vector<Variant>& variants_f32() {
   static const std::vector<Variant> v = [] {
     std::vector<Variant> r;
-#define MAKE_F32(TP, DPW, NW, NWIN, CC, RC)                                                        \
-  r.push_back(Variant{"win_tp" #TP "_dpw" #DPW "_nw" #NW, KIND_WIN_F32, TP, DPW, NW, NWIN, CC, RC});
+#define MAKE_F32(ID, TP, DPW, NW, NWIN, CC, RC, NB)                                                         \
+  r.push_back(Variant{"win_tp" #TP "_dpw" #DPW "_nw" #NW "_win" #NWIN "_cc" #CC "_buf" #NB, KIND_WIN_F32, TP,   \
+                      DPW, NW, NWIN,                                                                        \
+                      CC, RC, NB, ID});
     F32_VARIANTS(MAKE_F32)
 #undef MAKE_F32
     return r;
@@ -459,8 +603,8 @@ const std::vector<Variant>& variants_f32() {
 const std::vector<Variant>& variants_u8() {
   static const std::vector<Variant> v = [] {
     std::vector<Variant> r;
-#define MAKE_U8(Q, DPW, NW, CC, RC) \
-  r.push_back(Variant{"u8_q" #Q "_dpw" #DPW "_nw" #NW, KIND_TILE_U8, Q, DPW, NW, 0, CC, RC});
+#define MAKE_U8(ID, Q, DPW, NW, CC, RC) \
+  r.push_back(Variant{"u8_q" #Q "_dpw" #DPW "_nw" #NW "_cc" #CC, KIND_TILE_U8, Q, DPW, NW, 0, CC, RC, 1, ID});
     U8_VARIANTS(MAKE_U8)
 #undef MAKE_U8
     return r;
@@ -475,23 +619,23 @@ hipError_t launch_tiled(const Variant& v, const TileArgs& a, int nbeam, bool adj
   const dim3 block(64 * v.nwave);
   const bool weighted = adjoint ? false : (a.w_in != nullptr);
   if (v.kind == KIND_WIN_F32) {
-#define LAUNCH_F32(TP, DPW, NW, NWIN, CC, RC)                                                                     \
-  if (v.tp == TP && v.dpw == DPW && v.nwave == NW && v.nwin == NWIN && v.cc == CC && v.rowcap == RC) {             \
-    if (adjoint)                                                                                                    \
-      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, false, true>), grid, block, 0, s, a);             \
-    else if (weighted)                                                                                              \
-      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, true, false>), grid, block, 0, s, a);             \
-    else                                                                                                            \
-      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, false, false>), grid, block, 0, s, a);            \
-    return hipGetLastError();                                                                                       \
+#define LAUNCH_F32(ID, TP, DPW, NW, NWIN, CC, RC, NB)                                                     \
+  if (v.id == ID) {                                                                                       \
+    if (adjoint)                                                                                          \
+      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, false, true>), grid, block, 0, s, a); \
+    else if (weighted)                                                                                    \
+      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, true, false>), grid, block, 0, s, a); \
+    else                                                                                                  \
+      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, false, false>), grid, block, 0, s, a); \
+    return hipGetLastError();                                                                             \
   }
     F32_VARIANTS(LAUNCH_F32)
 #undef LAUNCH_F32
   } else {
-#define LAUNCH_U8(Q, DPW, NW, CC, RC)                                                     \
-  if (v.tp == Q && v.dpw == DPW && v.nwave == NW && v.cc == CC && v.rowcap == RC) {       \
-    hipLaunchKernelGGL((u8_kernel<Q, DPW, NW, CC, RC>), grid, block, 0, s, a);            \
-    return hipGetLastError();                                                             \
+#define LAUNCH_U8(ID, Q, DPW, NW, CC, RC)                                              \
+  if (v.id == ID) {                                                                    \
+    hipLaunchKernelGGL((u8_kernel<Q, DPW, NW, CC, RC>), grid, block, 0, s, a);         \
+    return hipGetLastError();                                                          \
   }
     U8_VARIANTS(LAUNCH_U8)
 #undef LAUNCH_U8
@@ -502,15 +646,15 @@ hipError_t launch_tiled(const Variant& v, const TileArgs& a, int nbeam, bool adj
 hipError_t launch_batched(const Variant& v, const BeamDesc* d_beams, bool weighted, const int32_t* d_order,
                           int64_t ntiles, int* d_counter, int grid, hipStream_t s) {
   const dim3 block(64 * v.nwave);
-#define LAUNCH_P(TP, DPW, NW, NWIN, CC, RC)                                                                       \
-  if (v.tp == TP && v.dpw == DPW && v.nwave == NW && v.nwin == NWIN && v.cc == CC && v.rowcap == RC) {             \
-    if (weighted)                                                                                                   \
-      hipLaunchKernelGGL((win_persistent<TP, DPW, NW, NWIN, CC, RC, true>), dim3(grid), block, 0, s, d_beams,     \
-                         d_order, ntiles, d_counter);                                                              \
-    else                                                                                                            \
-      hipLaunchKernelGGL((win_persistent<TP, DPW, NW, NWIN, CC, RC, false>), dim3(grid), block, 0, s, d_beams,    \
-                         d_order, ntiles, d_counter);                                                              \
-    return hipGetLastError();                                                                                       \
+#define LAUNCH_P(ID, TP, DPW, NW, NWIN, CC, RC, NB)                                                        \
+  if (v.id == ID) {                                                                                        \
+    if (weighted)                                                                                          \
+      hipLaunchKernelGGL((win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, true>), dim3(grid), block, 0, s,  \
+                         d_beams, d_order, ntiles, d_counter);                                             \
+    else                                                                                                   \
+      hipLaunchKernelGGL((win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, false>), dim3(grid), block, 0, s, \
+                         d_beams, d_order, ntiles, d_counter);                                             \
+    return hipGetLastError();                                                                              \
   }
   if (v.kind == KIND_WIN_F32) {
     F32_VARIANTS(LAUNCH_P)
@@ -521,12 +665,12 @@ hipError_t launch_batched(const Variant& v, const BeamDesc* d_beams, bool weight
 
 int batched_blocks_per_cu(const Variant& v) {
   int n = 0;
-#define OCC_P(TP, DPW, NW, NWIN, CC, RC)                                                                          \
-  if (v.tp == TP && v.dpw == DPW && v.nwave == NW && v.nwin == NWIN && v.cc == CC && v.rowcap == RC) {             \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, win_persistent<TP, DPW, NW, NWIN, CC, RC, false>,        \
-                                                     64 * NW, 0) != hipSuccess)                                    \
-      n = 1;                                                                                                        \
-    return n > 0 ? n : 1;                                                                                           \
+#define OCC_P(ID, TP, DPW, NW, NWIN, CC, RC, NB)                                                                 \
+  if (v.id == ID) {                                                                                              \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, false>,  \
+                                                     64 * NW, 0) != hipSuccess)                                   \
+      n = 1;                                                                                                     \
+    return n > 0 ? n : 1;                                                                                        \
   }
   if (v.kind == KIND_WIN_F32) {
     F32_VARIANTS(OCC_P)

@@ -24,6 +24,10 @@ namespace dd {
 // ---------------------------------------------------------------------------
 enum Kind { KIND_WIN_F32 = 0, KIND_TILE_U8 = 1 };
 
+// Longest row (samples) accepted: row byte sizes must fit a 32-bit buffer
+// range, and sample indices an int, with room for tile overhang.
+constexpr int64_t kMaxRow = (int64_t)1 << 29;
+
 struct Variant {
   const char* name;
   int kind;
@@ -33,9 +37,12 @@ struct Variant {
   int nwin;    // f32: window registers (0 for u8)
   int cc;      // input rows per LDS pass
   int rowcap;  // LDS row capacity (f32: elements, u8: bytes)
+  int nbuf;    // LDS buffers: 1 = synchronous staging, 2 = asynchronous double buffering
+  int id;      // index in the variant list
   int st() const { return kind == KIND_WIN_F32 ? 64 * tp : 256 * tp; }
   int dt() const { return nwave * dpw; }
-  int wav_ints() const { return kind == KIND_WIN_F32 ? (dpw > 8 ? 8 : 4) : (dpw > 8 ? 8 : 4); }
+  // ints per wave-table entry: f32 {win_start, nl, one offset per row} padded to 4/8/16; u8 packed u16 offsets
+  int wav_ints() const { return kind == KIND_WIN_F32 ? (dpw + 2 <= 4 ? 4 : dpw + 2 <= 8 ? 8 : 16) : 4; }
 };
 
 const std::vector<Variant>& variants_f32();
@@ -43,7 +50,7 @@ const std::vector<Variant>& variants_u8();
 
 // Host-built tile tables for one variant on one delay matrix.
 //   blk[row_tile][rows_in]            {stage_base, stage_len}
-//   wav[wave_tile][rows_in][wav_ints] f32: {win_start, nl, packed u8 offsets...}
+//   wav[wave_tile][rows_in][wav_ints] f32: {win_start, nl, offset of each row...}
 //                                      u8:  {packed u16 offsets...}
 struct Tables {
   int variant = -1;

@@ -93,7 +93,7 @@ static bool build_tables(const Variant& v, int rows_out, int rows_in, const Dela
               return false;
             }
             maxo = std::max(maxo, o);
-            e[2 + j / 4] |= (int32_t)((uint32_t)o << (8 * (j % 4)));
+            e[2 + j] = o;
           }
           const int nl = std::max(v.tp / 4 + 1, (v.tp + maxo + 3) / 4);
           e[0] = ws;
@@ -192,8 +192,8 @@ dedisp_status ensure_tables(dedisp_plan p, int dir, int vi, Tables** out) {
 
 // Default variant choice: the first of a preference list whose tables build.
 static int default_variant(dedisp_plan p, int dir) {
-  static const int pref_f32[] = {1, 0, 3, 4};
-  static const int pref_u8[] = {0, 4, 1, 2};
+  static const int pref_f32[] = {0, 1, 2, 4};
+  static const int pref_u8[] = {0, 2, 1, 4};
   const int* pref = dir == 1 ? pref_u8 : pref_f32;
   const int n = 4;
   for (int k = 0; k < n; ++k) {
@@ -375,8 +375,8 @@ dedisp_status dedisp_execute(dedisp_plan p, int32_t nbeam, int32_t nsamp, const 
   if (u8 && d_w) return fail(DEDISP_E_DTYPE, "weights are not supported for uint8 input");
   if (in_stride < (int64_t)nsamp + p->max_delay) return fail(DEDISP_E_SHAPE, "in_stride < nsamp + max_delay");
   if (out_stride < nsamp) return fail(DEDISP_E_SHAPE, "out_stride < nsamp");
-  if (in_stride > 0x7fffffff - 64 || (int64_t)nsamp + p->max_delay > 0x7fffffff - 65536)
-    return fail(DEDISP_E_SHAPE, "rows longer than 2^31 samples are not supported");
+  if (in_stride > kMaxRow || (int64_t)nsamp + p->max_delay > kMaxRow)
+    return fail(DEDISP_E_SHAPE, "rows longer than 2^29 samples are not supported");
   const int esz = u8 ? 1 : 4;
   if (!aligned16(d_in) || !aligned16(d_out) || (in_stride * esz) % 16 || (out_stride * 4) % 16 ||
       (d_w && ((uintptr_t)d_w & 3)))
@@ -441,7 +441,8 @@ dedisp_status dedisp_adjoint(dedisp_plan p, int32_t nbeam, int32_t nsamp, int32_
   if (d_grad_in && gi_stride < nin) return fail(DEDISP_E_SHAPE, "gi_stride < nin");
   if (d_in && in_stride < nin) return fail(DEDISP_E_SHAPE, "in_stride < nin");
   if ((int64_t)nsamp + p->max_delay > nin) return fail(DEDISP_E_SHAPE, "nin < nsamp + max_delay");
-  if (nin > 0x7fffffff - 65536) return fail(DEDISP_E_SHAPE, "rows longer than 2^31 samples are not supported");
+  if (nin > kMaxRow || g_stride > kMaxRow || (d_in && in_stride > kMaxRow) || (d_grad_in && gi_stride > kMaxRow))
+    return fail(DEDISP_E_SHAPE, "rows longer than 2^29 samples are not supported");
   if (!aligned16(d_g) || (g_stride * 4) % 16 || (d_grad_in && (!aligned16(d_grad_in) || (gi_stride * 4) % 16)) ||
       (d_in && (!aligned16(d_in) || (in_stride * 4) % 16)) || (d_w && ((uintptr_t)d_w & 3)))
     return fail(DEDISP_E_ALIGN, "pointers and row byte sizes must be multiples of 16 bytes");
