@@ -132,6 +132,8 @@ __device__ __forceinline__ void stage_f32(float4* lds4, const float* in, const T
 template <int NWAVE, int ROWCAP>
 __device__ __forceinline__ void stage_f32_async(float4* lds4, const float* in, const TileArgs& a,
                                                 const int32_t* blk, int c0, int ncc, int t0) {
+  // whole 64-lane loads stay inside the row's LDS slot
+  static_assert(ROWCAP % 256 == 0, "LDS rows hold a multiple of 64 float4");
   const int wave = wave_id(), lane = threadIdx.x & 63;
   for (int cl = wave; cl < ncc; cl += NWAVE) {
     const ent2_t bl = sload_entry2(blk + 2 * (c0 + cl));
@@ -173,6 +175,74 @@ __device__ __forceinline__ void fix_tail_async(float4* lds4, const float* in, co
     }
   }
 }
+
+// Store a finished tile (adjoint: scaled by w_out, with the wave's partial
+// sums of x * G for the weight gradient).
+template <int TP, int DPW, int NWAVE, bool ADJ>
+__device__ __forceinline__ void win_store(const TileArgs& a, const v16f* acc, int tt, int rt, int beam) {
+  constexpr int DT = NWAVE * DPW;
+  const int t0 = tt * 64 * TP;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  float* out = static_cast<float*>(a.out);
+  const int tl = t0 + lane * TP;
+#pragma unroll
+  for (int jj = 0; jj < DPW; ++jj) {
+    const int r = rt * DT + wave * DPW + jj;
+    if (r >= a.rows_out) break;
+    const float scale = (ADJ && a.w_out) ? a.w_out[r] : 1.f;
+    double gw = 0.0;
+    const float* xrow = nullptr;
+    if (ADJ && a.partial) xrow = a.x + (int64_t)beam * a.x_beam_stride + (int64_t)r * a.x_stride;
+    float* orow = out ? out + (int64_t)beam * a.out_beam_stride + (int64_t)r * a.out_stride : nullptr;
+#pragma unroll
+    for (int i4 = 0; i4 < TP / 4; ++i4) {
+      const int e0 = jj * TP + 4 * i4;
+      float4 v;
+      v.x = acc[(e0 + 0) / 16][(e0 + 0) % 16];
+      v.y = acc[(e0 + 1) / 16][(e0 + 1) % 16];
+      v.z = acc[(e0 + 2) / 16][(e0 + 2) % 16];
+      v.w = acc[(e0 + 3) / 16][(e0 + 3) % 16];
+      const int t = tl + 4 * i4;
+      if (ADJ && xrow) {
+        if (t + 4 <= a.nout) {
+          const float4 xv = *reinterpret_cast<const float4*>(xrow + t);
+          gw += (double)xv.x * (double)v.x;
+          gw += (double)xv.y * (double)v.y;
+          gw += (double)xv.z * (double)v.z;
+          gw += (double)xv.w * (double)v.w;
+        } else {
+          if (t + 0 < a.nout) gw += (double)xrow[t + 0] * (double)v.x;
+          if (t + 1 < a.nout) gw += (double)xrow[t + 1] * (double)v.y;
+          if (t + 2 < a.nout) gw += (double)xrow[t + 2] * (double)v.z;
+          if (t + 3 < a.nout) gw += (double)xrow[t + 3] * (double)v.w;
+        }
+      }
+      if (orow) {
+        if (ADJ) {
+          v.x *= scale;
+          v.y *= scale;
+          v.z *= scale;
+          v.w *= scale;
+        }
+        if (t + 4 <= a.nout) {
+          *reinterpret_cast<float4*>(orow + t) = v;
+        } else {
+          if (t + 0 < a.nout) orow[t + 0] = v.x;
+          if (t + 1 < a.nout) orow[t + 1] = v.y;
+          if (t + 2 < a.nout) orow[t + 2] = v.z;
+          if (t + 3 < a.nout) orow[t + 3] = v.w;
+        }
+      }
+    }
+    if (ADJ && xrow) {
+      // Fixed-order reduction over the 64 lanes of the wave.
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1) gw += __shfl_xor(gw, m, 64);
+      if (lane == 0) a.partial[((size_t)beam * a.n_time_tiles + tt) * a.rows_out + r] = gw;
+    }
+  }
+}
+
 
 // NBUF = 1: synchronous staging through registers, one LDS buffer.
 // NBUF = 2: asynchronous LDS loads into two buffers; the rows of pass p + 1
@@ -234,81 +304,106 @@ __device__ __forceinline__ void win_tile(const TileArgs& a, int tt, int rt, int 
     }
   }
 
-  // Epilogue: store the tile.
-  float* out = static_cast<float*>(a.out);
-  const int tl = t0 + lane * TP;
-#pragma unroll
-  for (int jj = 0; jj < DPW; ++jj) {
-    const int r = rt * DT + wave * DPW + jj;
-    if (r >= a.rows_out) break;
-    const float scale = (ADJ && a.w_out) ? a.w_out[r] : 1.f;
-    double gw = 0.0;
-    const float* xrow = nullptr;
-    if (ADJ && a.partial) xrow = a.x + (int64_t)beam * a.x_beam_stride + (int64_t)r * a.x_stride;
-    float* orow = out ? out + (int64_t)beam * a.out_beam_stride + (int64_t)r * a.out_stride : nullptr;
-#pragma unroll
-    for (int i4 = 0; i4 < TP / 4; ++i4) {
-      const int e0 = jj * TP + 4 * i4;
-      float4 v;
-      v.x = acc[(e0 + 0) / 16][(e0 + 0) % 16];
-      v.y = acc[(e0 + 1) / 16][(e0 + 1) % 16];
-      v.z = acc[(e0 + 2) / 16][(e0 + 2) % 16];
-      v.w = acc[(e0 + 3) / 16][(e0 + 3) % 16];
-      const int t = tl + 4 * i4;
-      if (ADJ && xrow) {
-        if (t + 4 <= a.nout) {
-          const float4 xv = *reinterpret_cast<const float4*>(xrow + t);
-          gw += (double)xv.x * (double)v.x;
-          gw += (double)xv.y * (double)v.y;
-          gw += (double)xv.z * (double)v.z;
-          gw += (double)xv.w * (double)v.w;
-        } else {
-          if (t + 0 < a.nout) gw += (double)xrow[t + 0] * (double)v.x;
-          if (t + 1 < a.nout) gw += (double)xrow[t + 1] * (double)v.y;
-          if (t + 2 < a.nout) gw += (double)xrow[t + 2] * (double)v.z;
-          if (t + 3 < a.nout) gw += (double)xrow[t + 3] * (double)v.w;
-        }
-      }
-      if (orow) {
-        if (ADJ) {
-          v.x *= scale;
-          v.y *= scale;
-          v.z *= scale;
-          v.w *= scale;
-        }
-        if (t + 4 <= a.nout) {
-          *reinterpret_cast<float4*>(orow + t) = v;
-        } else {
-          if (t + 0 < a.nout) orow[t + 0] = v.x;
-          if (t + 1 < a.nout) orow[t + 1] = v.y;
-          if (t + 2 < a.nout) orow[t + 2] = v.z;
-          if (t + 3 < a.nout) orow[t + 3] = v.w;
-        }
-      }
-    }
-    if (ADJ && xrow) {
-      // Fixed-order reduction over the 64 lanes of the wave.
-#pragma unroll
-      for (int m = 32; m >= 1; m >>= 1) gw += __shfl_xor(gw, m, 64);
-      if (lane == 0) a.partial[((size_t)beam * a.n_time_tiles + tt) * a.rows_out + r] = gw;
-    }
-  }
+  win_store<TP, DPW, NWAVE, ADJ>(a, acc, tt, rt, beam);
 }
 
-template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool WEIGHTED, bool ADJ>
+// Pipelined form: two register windows.  The step of input row c loads the
+// window of row c + 1 into one bank while it sums row c from the other, so
+// the LDS latency hides behind the adds.  The rows of pass p + 1 must have
+// landed before the last step of pass p (it loads the first window of pass
+// p + 1); by then every wave has finished reading pass p's rows, so pass p + 2
+// is staged into pass p's buffer right after that barrier.
+template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, bool WEIGHTED, bool ADJ>
+__device__ __forceinline__ void win_tile_pipe(const TileArgs& a, int tt, int rt, int beam, float4* lds4) {
+  constexpr int ST = 64 * TP;
+  constexpr int NACC = TP * DPW / 16;
+  constexpr int WI = EntT<DPW>::ints;
+  constexpr int BUF = CC * (ROWCAP / 4);  // float4 per LDS buffer
+  typedef typename EntT<DPW>::type E;
+  const int t0 = tt * ST;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  const int wt = rt * NWAVE + wave;
+  const int R = a.rows_in;
+  const int npass = (R + CC - 1) / CC;
+  const float* in = static_cast<const float*>(a.in) + (int64_t)beam * a.in_beam_stride;
+  const int32_t* __restrict__ blk = uniform_ptr(a.blk + (size_t)rt * R * 2);
+  const int32_t* __restrict__ wav = uniform_ptr(a.wav + (size_t)wt * R * WI);
+  const float* w_in = WEIGHTED ? uniform_ptr(a.w_in) : nullptr;
+  const uint32_t lane_base = (uint32_t)(uintptr_t)(LDS_AS float4*)(lds4) + (uint32_t)(lane * TP * 4);
+
+  v16f acc[NACC];
+#pragma unroll
+  for (int q = 0; q < NACC; ++q) acc[q] = (v16f)(0.f);
+  BankT<NWIN> ba = {}, bb = {};
+
+  // LDS byte address of this lane's window of row c starting at element ws
+  auto row_addr = [&](int c, int ws) -> uint32_t {
+    const int buf = (c / CC) & 1;
+    return lane_base + (uint32_t)(((buf * CC + c % CC) * ROWCAP + ws) * 4);
+  };
+
+  // entries (and weights) of rows c, c + 1; each step fetches row c + 2's
+  E e0 = sload_entry_t<E>(wav);
+  E e1 = sload_entry_t<E>(wav + (size_t)min(1, R - 1) * WI);
+  float w0 = WEIGHTED ? sload_f32(w_in) : 0.f;
+  float w1 = WEIGHTED ? sload_f32(w_in + min(1, R - 1)) : 0.f;
+
+  __syncthreads();  // a previous tile of this block is done with the LDS rows
+  stage_f32_async<NWAVE, ROWCAP>(lds4, in, a, blk, 0, min(CC, R), t0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  fix_tail_async<NWAVE, ROWCAP>(lds4, in, a, blk, 0, min(CC, R), t0);
+  __syncthreads();
+  if (npass > 1) stage_f32_async<NWAVE, ROWCAP>(lds4 + BUF, in, a, blk, CC, min(CC, R - CC), t0);
+  win_pload<TP, DPW, NWIN>(ba, bb, row_addr(0, e0[0]), e0[1]);
+
+  // Row c is summed from bank c & 1 (its table offsets include that bank's
+  // base) while row c + 1's window loads into the other.
+  for (int c = 0; c < R; ++c) {
+    const int cn = c + 1 < R ? c + 1 : c;
+    if (c + 1 < R && (c + 1) % CC == 0) {
+      const int pn = (c + 1) / CC;
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      fix_tail_async<NWAVE, ROWCAP>(lds4 + (pn & 1) * BUF, in, a, blk, pn * CC, min(CC, R - pn * CC), t0);
+      __syncthreads();
+      if (pn + 1 < npass)
+        stage_f32_async<NWAVE, ROWCAP>(lds4 + ((pn + 1) & 1) * BUF, in, a, blk, (pn + 1) * CC,
+                                       min(CC, R - (pn + 1) * CC), t0);
+    }
+    const int c2 = min(c + 2, R - 1);
+    E e2;
+    float w2 = 0.f;
+    win_pstep<TP, DPW, NWIN, WEIGHTED>(acc, ba, bb, row_addr(cn, e1[0]), e1[1], (c + 1) & 1, e0,
+                                       wav + (size_t)c2 * WI, e2, w0, WEIGHTED ? w_in + c2 : nullptr, w2);
+    e0 = e1;
+    e1 = e2;
+    w0 = w1;
+    w1 = w2;
+  }
+  win_store<TP, DPW, NWAVE, ADJ>(a, acc, tt, rt, beam);
+}
+
+template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool PIPE, bool WEIGHTED, bool ADJ>
+__device__ __forceinline__ void win_any(const TileArgs& a, int tt, int rt, int beam, float4* lds4) {
+  if constexpr (PIPE)
+    win_tile_pipe<TP, DPW, NWAVE, NWIN, CC, ROWCAP, WEIGHTED, ADJ>(a, tt, rt, beam, lds4);
+  else
+    win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, WEIGHTED, ADJ>(a, tt, rt, beam, lds4);
+}
+
+template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool PIPE, bool WEIGHTED, bool ADJ>
 __global__ __launch_bounds__(64 * NWAVE) void win_kernel(TileArgs a) {
   __shared__ float4 lds4[NBUF * CC * ROWCAP / 4];
   const int nblk = a.n_time_tiles * a.n_row_tiles;
   const int W = xcd_remap(blockIdx.x, nblk);
-  win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, WEIGHTED, ADJ>(a, W / a.n_row_tiles, W % a.n_row_tiles,
-                                                                   blockIdx.y, lds4);
+  win_any<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, PIPE, WEIGHTED, ADJ>(a, W / a.n_row_tiles, W % a.n_row_tiles,
+                                                                       blockIdx.y, lds4);
 }
 
 // Persistent form for batches of beams: blocks take tiles from a work table
 // (ordered by decreasing cost) through an atomic counter until it runs out.
 // Every beam shares the variant; per-beam pointers and tables come from its
 // descriptor.  The counter is cleared by a separate kernel before each launch.
-template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool WEIGHTED>
+template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool PIPE, bool WEIGHTED>
 __global__ __launch_bounds__(64 * NWAVE) void win_persistent(const BeamDesc* __restrict__ beams,
                                                              const int32_t* __restrict__ order, int64_t ntiles,
                                                              int* counter) {
@@ -324,7 +419,7 @@ __global__ __launch_bounds__(64 * NWAVE) void win_persistent(const BeamDesc* __r
     const int local = order[2 * k + 1];
     const TileArgs& a = beams[b].a;
     const int tt = local / a.n_row_tiles, rt = local % a.n_row_tiles;
-    win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, WEIGHTED, false>(a, tt, rt, 0, lds4);
+    win_any<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, PIPE, WEIGHTED, false>(a, tt, rt, 0, lds4);
   }
 }
 
@@ -378,25 +473,106 @@ __device__ __forceinline__ void stage_u8(uint4* lds, const uint8_t* in, const Ti
   }
 }
 
-template <int Q, int DPW, int NWAVE, int CC, int ROWCAP>
+// Synchronous staging of four byte-shifted copies of each row: copy s holds
+// row[k + s] at position k, so a dword holding four consecutive samples
+// starting at any byte offset o is the aligned dword (o >> 2) of copy o & 3.
+template <int NWAVE, int CC, int ROWCAP>
+__device__ __forceinline__ void stage_u8_shift4(uint4* lds, const uint8_t* in, const TileArgs& a, const int32_t* blk,
+                                                int c0, int ncc, int t0) {
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  for (int cl = wave; cl < ncc; cl += NWAVE) {
+    const ent2_t bl = sload_entry2(blk + 2 * (c0 + cl));
+    const uint8_t* src = in + (int64_t)(c0 + cl) * a.in_stride;
+    const int u0 = t0 + bl[0];
+    const int nv = bl[1] >> 4;
+    for (int v = lane; v < nv; v += 64) {
+      const int u = u0 + 16 * v;
+      uint32_t d[5];
+      if (u + 20 <= a.in_hi) {
+        const uint4 x = *reinterpret_cast<const uint4*>(src + u);
+        d[0] = x.x;
+        d[1] = x.y;
+        d[2] = x.z;
+        d[3] = x.w;
+        d[4] = *reinterpret_cast<const uint32_t*>(src + u + 16);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          uint32_t w = 0;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int uu = u + 4 * q + k;
+            w |= (uu < a.in_hi ? (uint32_t)src[uu] : 0u) << (8 * k);
+          }
+          d[q] = w;
+        }
+      }
+      lds[(0 * CC + cl) * (ROWCAP / 16) + v] = make_uint4(d[0], d[1], d[2], d[3]);
+#pragma unroll
+      for (int s = 1; s < 4; ++s) {
+        lds[(s * CC + cl) * (ROWCAP / 16) + v] =
+            make_uint4(__builtin_amdgcn_alignbyte(d[1], d[0], s), __builtin_amdgcn_alignbyte(d[2], d[1], s),
+                       __builtin_amdgcn_alignbyte(d[3], d[2], s), __builtin_amdgcn_alignbyte(d[4], d[3], s));
+      }
+    }
+  }
+}
+
+// Asynchronous staging of one pass: the rows (16-byte buffer loads writing
+// LDS directly; positions past the row end read as zero) and this wave's
+// table entries for the pass (one 16-byte entry per lane, lanes past the
+// pass read zero into the slack of the per-wave table slot).
+template <int NWAVE, int ROWCAP>
+__device__ __forceinline__ void stage_u8_async(uint4* lds, ent4_t* tabw, const uint8_t* in, const TileArgs& a,
+                                               const int32_t* blk, const int32_t* wav, int c0, int ncc, int t0) {
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  for (int cl = wave; cl < ncc; cl += NWAVE) {
+    const ent2_t bl = sload_entry2(blk + 2 * (c0 + cl));
+    const uint8_t* row = in + (int64_t)(c0 + cl) * a.in_stride;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)row, (short)0, a.in_hi, 0x00020000);
+    const int u0 = t0 + bl[0];
+    const int nv = bl[1] >> 4;
+    for (int v0 = 0; v0 < nv; v0 += 64) {
+      if (v0 + lane < nv)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (LDS_AS void*)(lds + cl * (ROWCAP / 16) + v0), 16,
+                                                 u0 + 16 * (v0 + lane), 0, 0, 0);
+    }
+  }
+  const __amdgpu_buffer_rsrc_t rt =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(wav + (size_t)c0 * 4), (short)0, ncc * 16, 0x00020000);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(rt, (LDS_AS void*)tabw, 16, lane * 16, 0, 0, 0);
+}
+
+// One block walks `tiles_per_block` consecutive time tiles of one DM tile.
+// NBUF = 1: synchronous staging; NBUF = 2: the rows of the next (time tile,
+// pass) step are loaded into the second buffer while the current one is
+// summed, and the finished tile's stores drain behind the next tile's work.
+template <int Q, int DPW, int NWAVE, int CC, int ROWCAP, int NBUF>
 __global__ __launch_bounds__(64 * NWAVE) void u8_kernel(TileArgs a) {
   constexpr int ST = 256 * Q;
   constexpr int DT = NWAVE * DPW;
   constexpr int WI = 4;  // packed 16-bit offsets, DPW <= 8
   static_assert(DPW <= 8, "uint8 variants pack at most 8 offsets");
-  __shared__ uint4 lds[CC * ROWCAP / 16];
-  const int nblk = a.n_time_tiles * a.n_row_tiles;
+  typedef ent4_t E;
+  __shared__ uint4 lds[NBUF * CC * ROWCAP / 16];
+  __shared__ E tab[NBUF][NWAVE][NBUF == 2 ? 64 : CC];
+  const int tpb = NBUF == 2 ? a.tiles_per_block : 1;
+  const int ngroups = (a.n_time_tiles + tpb - 1) / tpb;
+  const int nblk = ngroups * a.n_row_tiles;
   const int W = xcd_remap(blockIdx.x, nblk);
-  const int tt = W / a.n_row_tiles, rt = W % a.n_row_tiles;
+  const int grp = W / a.n_row_tiles, rt = W % a.n_row_tiles;
+  const int tt0 = grp * tpb;
+  const int ntile = min(tpb, a.n_time_tiles - tt0);
   const int beam = blockIdx.y;
-  const int t0 = tt * ST;
   const int wave = wave_id(), lane = threadIdx.x & 63;
   const int wt = rt * NWAVE + wave;
   const uint8_t* in = static_cast<const uint8_t*>(a.in) + (int64_t)beam * a.in_beam_stride;
-  const int32_t* blk = a.blk + (size_t)rt * a.rows_in * 2;
+  const int32_t* blk = uniform_ptr(a.blk + (size_t)rt * a.rows_in * 2);
   const int32_t* __restrict__ wav = uniform_ptr(a.wav + (size_t)wt * a.rows_in * WI);
   const uint32_t* lds32 = reinterpret_cast<const uint32_t*>(lds);
-  typedef ent4_t E;
+  int32_t* out = static_cast<int32_t*>(a.out) + (int64_t)beam * a.out_beam_stride;
+  const int npass = (a.rows_in + CC - 1) / CC;
+  const int nsteps = ntile * npass;
 
   int acc[DPW][Q][4];
 #pragma unroll
@@ -406,33 +582,48 @@ __global__ __launch_bounds__(64 * NWAVE) void u8_kernel(TileArgs a) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) acc[j][q][k] = 0;
 
-  // The wave's offsets for the rows of a pass are copied into LDS with the
-  // rows; each step reads the next row's entry (a broadcast LDS read) one
-  // step ahead of its use.
-  static_assert(WI == 4, "uint8 variants use 4-int table entries");
-  __shared__ E tab[NWAVE][CC];
-  for (int c0 = 0; c0 < a.rows_in; c0 += CC) {
+  if (NBUF == 2) stage_u8_async<NWAVE, ROWCAP>(lds, tab[0][wave], in, a, blk, wav, 0, min(CC, a.rows_in), tt0 * ST);
+  for (int s = 0; s < nsteps; ++s) {
+    const int k = s / npass, p = s - k * npass;
+    const int t0 = (tt0 + k) * ST;
+    const int c0 = p * CC;
     const int ncc = min(CC, a.rows_in - c0);
-    __syncthreads();
-    stage_u8<NWAVE, ROWCAP>(lds, in, a, blk, c0, ncc, t0);
-    if (lane < ncc) tab[wave][lane] = *reinterpret_cast<const E*>(wav + (size_t)(c0 + lane) * WI);
-    __syncthreads();
-    E cur = tab[wave][0];
+    const int buf = NBUF == 2 ? (s & 1) : 0;
+    if (NBUF == 1) {
+      // The wave's offsets for the rows of a pass are copied into LDS with
+      // the rows.
+      __syncthreads();
+      stage_u8<NWAVE, ROWCAP>(lds, in, a, blk, c0, ncc, t0);
+      if (lane < ncc) tab[0][wave][lane] = *reinterpret_cast<const E*>(wav + (size_t)(c0 + lane) * WI);
+      __syncthreads();
+    } else {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+      if (s + 1 < nsteps) {
+        const int k1 = (s + 1) / npass, p1 = s + 1 - k1 * npass;
+        stage_u8_async<NWAVE, ROWCAP>(lds + ((s + 1) & 1) * CC * (ROWCAP / 16), tab[(s + 1) & 1][wave], in, a, blk,
+                                      wav, p1 * CC, min(CC, a.rows_in - p1 * CC), (tt0 + k1) * ST);
+      }
+    }
+    const uint32_t* rows = lds32 + buf * CC * (ROWCAP / 4);
+    E cur = tab[buf][wave][0];
     for (int cl = 0; cl < ncc; ++cl) {
-      const E nxt = tab[wave][min(cl + 1, ncc - 1)];
-      const uint32_t* row = lds32 + cl * (ROWCAP / 4);
+      // each step reads the next row's entry (a broadcast LDS read) one step
+      // ahead of its use
+      const E nxt = tab[buf][wave][min(cl + 1, ncc - 1)];
+      const uint32_t* row = rows + cl * (ROWCAP / 4);
       uint32_t cw[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) cw[k] = (uint32_t)__builtin_amdgcn_readfirstlane(cur[k]);
+      for (int q = 0; q < 4; ++q) cw[q] = (uint32_t)__builtin_amdgcn_readfirstlane(cur[q]);
 #pragma unroll
       for (int jj = 0; jj < DPW; ++jj) {
         const uint32_t o = (cw[jj >> 1] >> (16 * (jj & 1))) & 0xFFFFu;
         const uint32_t sh = o & 3u;
-        const uint32_t* p = row + (o >> 2) + lane;
+        const uint32_t* pr = row + (o >> 2) + lane;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-          const uint32_t d0 = p[64 * q];
-          const uint32_t d1 = p[64 * q + 1];
+          const uint32_t d0 = pr[64 * q];
+          const uint32_t d1 = pr[64 * q + 1];
           const uint32_t v = __builtin_amdgcn_alignbyte(d1, d0, sh);
           acc[jj][q][0] += (int)(v & 0xFFu);
           acc[jj][q][1] += (int)((v >> 8) & 0xFFu);
@@ -442,26 +633,177 @@ __global__ __launch_bounds__(64 * NWAVE) void u8_kernel(TileArgs a) {
       }
       cur = nxt;
     }
+    if (p == npass - 1) {
+#pragma unroll
+      for (int jj = 0; jj < DPW; ++jj) {
+        const int r = rt * DT + wave * DPW + jj;
+        if (r < a.rows_out) {
+          int32_t* orow = out + (int64_t)r * a.out_stride;
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            const int t = t0 + 4 * lane + 256 * q;
+            if (t + 4 <= a.nout) {
+              __builtin_nontemporal_store(acc[jj][q][0], orow + t + 0);
+              __builtin_nontemporal_store(acc[jj][q][1], orow + t + 1);
+              __builtin_nontemporal_store(acc[jj][q][2], orow + t + 2);
+              __builtin_nontemporal_store(acc[jj][q][3], orow + t + 3);
+            } else {
+#pragma unroll
+              for (int e = 0; e < 4; ++e)
+                if (t + e < a.nout) orow[t + e] = acc[jj][q][e];
+            }
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[jj][q][e] = 0;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// uint8 -> int32 tile engine on byte-shifted rows.  Each input row is staged
+// as four copies shifted by 0..3 bytes (stage_u8_shift4), so the four samples
+// a lane needs at any delay are one aligned LDS dword: one 4-byte LDS read
+// per 4 adds.  The bytes are split into two packed 16-bit pairs with byte
+// permutes (samples {0, 2} and {1, 3}) and two input rows are summed per
+// three-operand add, 0.75 vector operations per add.  A 16-bit lane holds
+// the sum of at most 257 bytes; WIDE variants move the packed sums into
+// int32 accumulators every 256 input rows, the others accept at most 257
+// input rows.  Sums are exact integers, so the order does not matter.
+// ---------------------------------------------------------------------------
+template <int Q, int DPW, int NWAVE, int CC, int ROWCAP, bool WIDE>
+__global__ __launch_bounds__(64 * NWAVE) void u8s_kernel(TileArgs a) {
+  constexpr int ST = 256 * Q;
+  constexpr int DT = NWAVE * DPW;
+  constexpr int RW = ROWCAP / 4;  // dwords per copy of a row
+  static_assert(DPW <= 8 && CC % 2 == 0 && 256 % CC == 0, "unsupported shape");
+  typedef ent4_t E;
+  constexpr uint32_t SEL_EVEN = 0x0C020C00u;  // bytes {0, 2} into 16-bit lanes
+  constexpr uint32_t SEL_ODD = 0x0C030C01u;   // bytes {1, 3}
+  __shared__ uint4 lds[4 * CC * ROWCAP / 16];
+  __shared__ E tab[NWAVE][CC];
+  const int nblk = a.n_time_tiles * a.n_row_tiles;
+  const int W = xcd_remap(blockIdx.x, nblk);
+  const int tt = W / a.n_row_tiles, rt = W % a.n_row_tiles;
+  const int beam = blockIdx.y;
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  const int wt = rt * NWAVE + wave;
+  const int t0 = tt * ST;
+  const uint8_t* in = static_cast<const uint8_t*>(a.in) + (int64_t)beam * a.in_beam_stride;
+  const int32_t* blk = uniform_ptr(a.blk + (size_t)rt * a.rows_in * 2);
+  const int32_t* __restrict__ wav = uniform_ptr(a.wav + (size_t)wt * a.rows_in * 4);
+  const uint32_t* lds32 = reinterpret_cast<const uint32_t*>(lds) + lane;
+  int32_t* out = static_cast<int32_t*>(a.out) + (int64_t)beam * a.out_beam_stride;
+  const int npass = (a.rows_in + CC - 1) / CC;
+
+  uint32_t ev[DPW][Q], od[DPW][Q];
+  int acc[WIDE ? DPW : 1][WIDE ? Q : 1][4];
+#pragma unroll
+  for (int j = 0; j < DPW; ++j)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      ev[j][q] = od[j][q] = 0u;
+      if (WIDE)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[WIDE ? j : 0][WIDE ? q : 0][k] = 0;
+    }
+
+  // dword offset of the lane-0 read of output row jj in staged row cl
+  auto base_of = [&](const uint32_t* cw, int jj, int cl) -> int {
+    const uint32_t o = (cw[jj >> 1] >> (16 * (jj & 1))) & 0xFFFFu;
+    return (int)(((o & 3u) * CC + cl) * RW + (o >> 2));
+  };
+
+  for (int p = 0; p < npass; ++p) {
+    const int c0 = p * CC;
+    const int ncc = min(CC, a.rows_in - c0);
+    __syncthreads();
+    stage_u8_shift4<NWAVE, CC, ROWCAP>(lds, in, a, blk, c0, ncc, t0);
+    if (lane < ncc) tab[wave][lane] = *reinterpret_cast<const E*>(wav + (size_t)(c0 + lane) * 4);
+    __syncthreads();
+    int cl = 0;
+    for (; cl + 1 < ncc; cl += 2) {
+      const E e0 = tab[wave][cl], e1 = tab[wave][cl + 1];
+      uint32_t c0w[4], c1w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        c0w[q] = (uint32_t)__builtin_amdgcn_readfirstlane(e0[q]);
+        c1w[q] = (uint32_t)__builtin_amdgcn_readfirstlane(e1[q]);
+      }
+#pragma unroll
+      for (int jj = 0; jj < DPW; ++jj) {
+        const uint32_t* p0 = lds32 + base_of(c0w, jj, cl);
+        const uint32_t* p1 = lds32 + base_of(c1w, jj, cl + 1);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const uint32_t v0 = p0[64 * q], v1 = p1[64 * q];
+          ev[jj][q] += __builtin_amdgcn_perm(0u, v0, SEL_EVEN) + __builtin_amdgcn_perm(0u, v1, SEL_EVEN);
+          od[jj][q] += __builtin_amdgcn_perm(0u, v0, SEL_ODD) + __builtin_amdgcn_perm(0u, v1, SEL_ODD);
+        }
+      }
+    }
+    if (cl < ncc) {
+      const E e0 = tab[wave][cl];
+      uint32_t c0w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) c0w[q] = (uint32_t)__builtin_amdgcn_readfirstlane(e0[q]);
+#pragma unroll
+      for (int jj = 0; jj < DPW; ++jj) {
+        const uint32_t* p0 = lds32 + base_of(c0w, jj, cl);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const uint32_t v0 = p0[64 * q];
+          ev[jj][q] += __builtin_amdgcn_perm(0u, v0, SEL_EVEN);
+          od[jj][q] += __builtin_amdgcn_perm(0u, v0, SEL_ODD);
+        }
+      }
+    }
+    if (WIDE && (((p + 1) * CC) % 256 == 0 || p == npass - 1)) {
+#pragma unroll
+      for (int j = 0; j < DPW; ++j)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          int* A = acc[WIDE ? j : 0][WIDE ? q : 0];
+          A[0] += (int)(ev[j][q] & 0xFFFFu);
+          A[1] += (int)(od[j][q] & 0xFFFFu);
+          A[2] += (int)(ev[j][q] >> 16);
+          A[3] += (int)(od[j][q] >> 16);
+          ev[j][q] = od[j][q] = 0u;
+        }
+    }
   }
 
-  int32_t* out = static_cast<int32_t*>(a.out) + (int64_t)beam * a.out_beam_stride;
 #pragma unroll
   for (int jj = 0; jj < DPW; ++jj) {
     const int r = rt * DT + wave * DPW + jj;
-    if (r >= a.rows_out) break;
-    int32_t* orow = out + (int64_t)r * a.out_stride;
+    if (r < a.rows_out) {
+      int32_t* orow = out + (int64_t)r * a.out_stride;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int t = t0 + 4 * lane + 256 * q;
-      if (t + 4 <= a.nout) {
-        __builtin_nontemporal_store(acc[jj][q][0], orow + t + 0);
-        __builtin_nontemporal_store(acc[jj][q][1], orow + t + 1);
-        __builtin_nontemporal_store(acc[jj][q][2], orow + t + 2);
-        __builtin_nontemporal_store(acc[jj][q][3], orow + t + 3);
-      } else {
+      for (int q = 0; q < Q; ++q) {
+        int s[4];
+        if (WIDE) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-          if (t + k < a.nout) orow[t + k] = acc[jj][q][k];
+          for (int e = 0; e < 4; ++e) s[e] = acc[WIDE ? jj : 0][WIDE ? q : 0][e];
+        } else {
+          s[0] = (int)(ev[jj][q] & 0xFFFFu);
+          s[1] = (int)(od[jj][q] & 0xFFFFu);
+          s[2] = (int)(ev[jj][q] >> 16);
+          s[3] = (int)(od[jj][q] >> 16);
+        }
+        const int t = t0 + 4 * lane + 256 * q;
+        if (t + 4 <= a.nout) {
+          __builtin_nontemporal_store(s[0], orow + t + 0);
+          __builtin_nontemporal_store(s[1], orow + t + 1);
+          __builtin_nontemporal_store(s[2], orow + t + 2);
+          __builtin_nontemporal_store(s[3], orow + t + 3);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (t + e < a.nout) orow[t + e] = s[e];
+        }
       }
     }
   }
@@ -558,41 +900,64 @@ __global__ __launch_bounds__(256) void reduce_gradw_kernel(const double* __restr
 // Variant tables and launchers.
 // ---------------------------------------------------------------------------
 // (index, TP samples per lane, DPW rows per wave, NWAVE, NWIN window registers,
-//  CC rows per LDS pass, ROWCAP floats per LDS row, NBUF LDS buffers)
+//  CC rows per LDS pass, ROWCAP floats per LDS row, NBUF LDS buffers, PIPE:
+//  two register windows with the next row's loads in flight)
 // A lane owns TP consecutive samples; TP/4 odd (12, 20) keeps its 16-byte LDS
 // reads free of bank conflicts.
-#define F32_VARIANTS(X)                                          \
-  X(0, 12, 4, 4, 36, 8, 1024, 1)   /* 16 DMs x 768             */ \
-  X(1, 12, 4, 4, 48, 8, 1024, 1)   /* 16 DMs x 768, wide spans */ \
-  X(2, 8, 8, 4, 64, 8, 1024, 1)    /* 32 DMs x 512             */ \
-  X(3, 16, 8, 4, 72, 8, 2048, 1)   /* 32 DMs x 1024            */ \
-  X(4, 8, 4, 4, 48, 16, 1024, 1)   /* 16 DMs x 512             */ \
-  X(5, 16, 4, 4, 64, 8, 2048, 1)   /* 16 DMs x 1024            */ \
-  X(6, 12, 4, 4, 36, 4, 1024, 2)   /* 16 DMs x 768, async      */ \
-  X(7, 12, 8, 4, 56, 4, 1024, 2)   /* 32 DMs x 768, async      */ \
-  X(8, 20, 4, 4, 44, 4, 1536, 2)   /* 16 DMs x 1280, async     */ \
-  X(9, 12, 4, 8, 36, 4, 1024, 2)   /* 32 DMs x 768, async      */ \
-  X(10, 12, 8, 8, 56, 4, 1280, 2)  /* 64 DMs x 768, async      */ \
-  X(11, 12, 4, 4, 48, 4, 1024, 2)  /* 16 DMs x 768, async      */ \
-  X(12, 8, 8, 4, 64, 4, 1024, 2)   /* 32 DMs x 512, async      */
+#define F32_VARIANTS(X)                                             \
+  X(0, 12, 4, 4, 36, 8, 1024, 1, 0)   /* 16 DMs x 768             */ \
+  X(1, 12, 4, 4, 48, 8, 1024, 1, 0)   /* 16 DMs x 768, wide spans */ \
+  X(2, 8, 8, 4, 64, 8, 1024, 1, 0)    /* 32 DMs x 512             */ \
+  X(3, 16, 8, 4, 72, 8, 2048, 1, 0)   /* 32 DMs x 1024            */ \
+  X(4, 8, 4, 4, 48, 16, 1024, 1, 0)   /* 16 DMs x 512             */ \
+  X(5, 16, 4, 4, 64, 8, 2048, 1, 0)   /* 16 DMs x 1024            */ \
+  X(6, 12, 4, 4, 36, 4, 1024, 2, 0)   /* 16 DMs x 768, async      */ \
+  X(7, 12, 8, 4, 56, 4, 1024, 2, 0)   /* 32 DMs x 768, async      */ \
+  X(8, 20, 4, 4, 44, 4, 1536, 2, 0)   /* 16 DMs x 1280, async     */ \
+  X(9, 12, 4, 8, 36, 4, 1024, 2, 0)   /* 32 DMs x 768, async      */ \
+  X(10, 12, 8, 8, 56, 4, 1280, 2, 0)  /* 64 DMs x 768, async      */ \
+  X(11, 12, 4, 4, 48, 4, 1024, 2, 0)  /* 16 DMs x 768, async      */ \
+  X(12, 8, 8, 4, 64, 4, 1024, 2, 0)   /* 32 DMs x 512, async      */ \
+  X(13, 20, 4, 4, 44, 4, 1536, 2, 1)  /* 16 DMs x 1280, pipelined */ \
+  X(14, 20, 4, 8, 44, 8, 1536, 2, 1)  /* 32 DMs x 1280, pipelined */ \
+  X(15, 12, 4, 4, 36, 4, 1024, 2, 1)  /* 16 DMs x 768, pipelined  */ \
+  X(16, 12, 4, 6, 36, 6, 1024, 2, 1)  /* 24 DMs x 768, pipelined  */ \
+  X(17, 12, 8, 4, 56, 4, 1024, 2, 1)  /* 32 DMs x 768, pipelined  */ \
+  X(18, 12, 8, 8, 56, 8, 1280, 2, 1)  /* 64 DMs x 768, pipelined  */
 
 // (index, Q dwords per lane, DPW, NWAVE, CC rows per LDS pass, ROWCAP bytes)
-#define U8_VARIANTS(X)                            \
-  X(0, 4, 4, 4, 16, 2048) /* 16 DMs x 1024 */     \
-  X(1, 4, 2, 4, 32, 1536) /*  8 DMs x 1024 */     \
-  X(2, 2, 4, 4, 16, 1536) /* 16 DMs x 512  */     \
-  X(3, 4, 4, 4, 32, 2048) /* 16 DMs x 1024 */     \
-  X(4, 2, 2, 4, 32, 1024) /*  8 DMs x 512  */     \
-  X(5, 4, 8, 4, 16, 4096) /* 32 DMs x 1024 */     \
-  X(6, 4, 4, 8, 16, 4096) /* 32 DMs x 1024 */
+#define U8_VARIANTS(X)                                      \
+  X(0, 4, 4, 4, 16, 2048, 1) /* 16 DMs x 1024          */   \
+  X(1, 4, 2, 4, 32, 1536, 1) /*  8 DMs x 1024          */   \
+  X(2, 2, 4, 4, 16, 1536, 1) /* 16 DMs x 512           */   \
+  X(3, 4, 4, 4, 32, 2048, 1) /* 16 DMs x 1024          */   \
+  X(4, 2, 2, 4, 32, 1024, 1) /*  8 DMs x 512           */   \
+  X(5, 4, 8, 4, 16, 4096, 1) /* 32 DMs x 1024          */   \
+  X(6, 4, 4, 8, 16, 4096, 1) /* 32 DMs x 1024          */   \
+  X(7, 2, 4, 4, 16, 1152, 2) /* 16 DMs x 512, async    */   \
+  X(8, 4, 4, 4, 16, 1664, 2) /* 16 DMs x 1024, async   */   \
+  X(9, 4, 4, 8, 8, 2304, 2)  /* 32 DMs x 1024, async   */   \
+  X(10, 2, 8, 4, 16, 1792, 2) /* 32 DMs x 512, async   */   \
+  X(11, 2, 4, 4, 32, 1152, 2) /* 16 DMs x 512, async   */
+
+// Byte-shifted variants: (index, Q, DPW, NWAVE, CC, ROWCAP bytes per copy, WIDE)
+#define U8S_VARIANTS(X)                                      \
+  X(12, 4, 4, 4, 8, 1792, false) /* 16 DMs x 1024      */   \
+  X(13, 2, 4, 4, 8, 1280, false) /* 16 DMs x 512       */   \
+  X(14, 4, 4, 4, 4, 1792, false) /* 16 DMs x 1024      */   \
+  X(15, 2, 8, 4, 8, 1792, false) /* 32 DMs x 512       */   \
+  X(16, 4, 2, 4, 8, 1536, false) /*  8 DMs x 1024      */   \
+  X(17, 2, 4, 8, 4, 1792, false) /* 32 DMs x 512       */   \
+  X(18, 4, 4, 4, 8, 1792, true)  /* 16 DMs x 1024, wide */  \
+  X(19, 2, 4, 4, 8, 1280, true)  /* 16 DMs x 512, wide  */
 
 const std::vector<Variant>& variants_f32() {
   static const std::vector<Variant> v = [] {
     std::vector<Variant> r;
-#define MAKE_F32(ID, TP, DPW, NW, NWIN, CC, RC, NB)                                                         \
-  r.push_back(Variant{"win_tp" #TP "_dpw" #DPW "_nw" #NW "_win" #NWIN "_cc" #CC "_buf" #NB, KIND_WIN_F32, TP,   \
-                      DPW, NW, NWIN,                                                                        \
-                      CC, RC, NB, ID});
+#define MAKE_F32(ID, TP, DPW, NW, NWIN, CC, RC, NB, PIPE)                                                  \
+  r.push_back(Variant{PIPE ? "win_tp" #TP "_dpw" #DPW "_nw" #NW "_win" #NWIN "_cc" #CC "_pipe"               \
+                           : "win_tp" #TP "_dpw" #DPW "_nw" #NW "_win" #NWIN "_cc" #CC "_buf" #NB,            \
+                      KIND_WIN_F32, TP, DPW, NW, NWIN, CC, RC, NB, ID, PIPE});
     F32_VARIANTS(MAKE_F32)
 #undef MAKE_F32
     return r;
@@ -603,42 +968,60 @@ const std::vector<Variant>& variants_f32() {
 const std::vector<Variant>& variants_u8() {
   static const std::vector<Variant> v = [] {
     std::vector<Variant> r;
-#define MAKE_U8(ID, Q, DPW, NW, CC, RC) \
-  r.push_back(Variant{"u8_q" #Q "_dpw" #DPW "_nw" #NW "_cc" #CC, KIND_TILE_U8, Q, DPW, NW, 0, CC, RC, 1, ID});
+#define MAKE_U8(ID, Q, DPW, NW, CC, RC, NB)                                                                 \
+  r.push_back(Variant{"u8_q" #Q "_dpw" #DPW "_nw" #NW "_cc" #CC "_buf" #NB, KIND_TILE_U8, Q, DPW, NW, 0, CC, RC, NB, \
+                      ID});
     U8_VARIANTS(MAKE_U8)
 #undef MAKE_U8
+#define MAKE_U8S(ID, Q, DPW, NW, CC, RC, WIDE)                                                               \
+  r.push_back(Variant{WIDE ? "u8s_q" #Q "_dpw" #DPW "_nw" #NW "_cc" #CC "_wide" : "u8s_q" #Q "_dpw" #DPW "_nw" #NW \
+                                                                                     "_cc" #CC,             \
+                      KIND_TILE_U8, Q, DPW, NW, 0, CC, RC, 1, ID, WIDE ? 2 : 1});
+    U8S_VARIANTS(MAKE_U8S)
+#undef MAKE_U8S
     return r;
   }();
   return v;
 }
 
 hipError_t launch_tiled(const Variant& v, const TileArgs& a, int nbeam, bool adjoint, hipStream_t s) {
-  const int64_t nblk = (int64_t)a.n_time_tiles * a.n_row_tiles;
+  // uint8 double-buffered blocks walk tiles_per_block time tiles each
+  const int tpb = (v.kind == KIND_TILE_U8 && v.nbuf == 2) ? a.tiles_per_block : 1;
+  if (tpb < 1) return hipErrorInvalidConfiguration;
+  const int64_t nblk = (int64_t)((a.n_time_tiles + tpb - 1) / tpb) * a.n_row_tiles;
   if (nblk < 1 || nblk > 0x7fffffff || nbeam < 1 || nbeam > 65535) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)nblk, (unsigned)nbeam);
   const dim3 block(64 * v.nwave);
   const bool weighted = adjoint ? false : (a.w_in != nullptr);
   if (v.kind == KIND_WIN_F32) {
-#define LAUNCH_F32(ID, TP, DPW, NW, NWIN, CC, RC, NB)                                                     \
-  if (v.id == ID) {                                                                                       \
-    if (adjoint)                                                                                          \
-      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, false, true>), grid, block, 0, s, a); \
-    else if (weighted)                                                                                    \
-      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, true, false>), grid, block, 0, s, a); \
-    else                                                                                                  \
-      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, false, false>), grid, block, 0, s, a); \
-    return hipGetLastError();                                                                             \
+#define LAUNCH_F32(ID, TP, DPW, NW, NWIN, CC, RC, NB, PIPE)                                                     \
+  if (v.id == ID) {                                                                                             \
+    if (adjoint)                                                                                                \
+      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, PIPE, false, true>), grid, block, 0, s, a); \
+    else if (weighted)                                                                                          \
+      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, PIPE, true, false>), grid, block, 0, s, a); \
+    else                                                                                                        \
+      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, PIPE, false, false>), grid, block, 0, s,    \
+                         a);                                                                                    \
+    return hipGetLastError();                                                                                   \
   }
     F32_VARIANTS(LAUNCH_F32)
 #undef LAUNCH_F32
   } else {
-#define LAUNCH_U8(ID, Q, DPW, NW, CC, RC)                                              \
+#define LAUNCH_U8(ID, Q, DPW, NW, CC, RC, NB)                                          \
   if (v.id == ID) {                                                                    \
-    hipLaunchKernelGGL((u8_kernel<Q, DPW, NW, CC, RC>), grid, block, 0, s, a);         \
+    hipLaunchKernelGGL((u8_kernel<Q, DPW, NW, CC, RC, NB>), grid, block, 0, s, a);     \
     return hipGetLastError();                                                          \
   }
     U8_VARIANTS(LAUNCH_U8)
 #undef LAUNCH_U8
+#define LAUNCH_U8S(ID, Q, DPW, NW, CC, RC, WIDE)                                       \
+  if (v.id == ID) {                                                                    \
+    hipLaunchKernelGGL((u8s_kernel<Q, DPW, NW, CC, RC, WIDE>), grid, block, 0, s, a);  \
+    return hipGetLastError();                                                          \
+  }
+    U8S_VARIANTS(LAUNCH_U8S)
+#undef LAUNCH_U8S
   }
   return hipErrorInvalidDeviceFunction;
 }
@@ -646,15 +1029,15 @@ hipError_t launch_tiled(const Variant& v, const TileArgs& a, int nbeam, bool adj
 hipError_t launch_batched(const Variant& v, const BeamDesc* d_beams, bool weighted, const int32_t* d_order,
                           int64_t ntiles, int* d_counter, int grid, hipStream_t s) {
   const dim3 block(64 * v.nwave);
-#define LAUNCH_P(ID, TP, DPW, NW, NWIN, CC, RC, NB)                                                        \
-  if (v.id == ID) {                                                                                        \
-    if (weighted)                                                                                          \
-      hipLaunchKernelGGL((win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, true>), dim3(grid), block, 0, s,  \
-                         d_beams, d_order, ntiles, d_counter);                                             \
-    else                                                                                                   \
-      hipLaunchKernelGGL((win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, false>), dim3(grid), block, 0, s, \
-                         d_beams, d_order, ntiles, d_counter);                                             \
-    return hipGetLastError();                                                                              \
+#define LAUNCH_P(ID, TP, DPW, NW, NWIN, CC, RC, NB, PIPE)                                                        \
+  if (v.id == ID) {                                                                                              \
+    if (weighted)                                                                                                \
+      hipLaunchKernelGGL((win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, PIPE, true>), dim3(grid), block, 0, s,  \
+                         d_beams, d_order, ntiles, d_counter);                                                   \
+    else                                                                                                         \
+      hipLaunchKernelGGL((win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, PIPE, false>), dim3(grid), block, 0, s, \
+                         d_beams, d_order, ntiles, d_counter);                                                   \
+    return hipGetLastError();                                                                                    \
   }
   if (v.kind == KIND_WIN_F32) {
     F32_VARIANTS(LAUNCH_P)
@@ -665,11 +1048,11 @@ hipError_t launch_batched(const Variant& v, const BeamDesc* d_beams, bool weight
 
 int batched_blocks_per_cu(const Variant& v) {
   int n = 0;
-#define OCC_P(ID, TP, DPW, NW, NWIN, CC, RC, NB)                                                                 \
-  if (v.id == ID) {                                                                                              \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, false>,  \
-                                                     64 * NW, 0) != hipSuccess)                                   \
-      n = 1;                                                                                                     \
+#define OCC_P(ID, TP, DPW, NW, NWIN, CC, RC, NB, PIPE)                                                   \
+  if (v.id == ID) {                                                                                       \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(                                                     \
+            &n, win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, PIPE, false>, 64 * NW, 0) != hipSuccess)     \
+      n = 1;                                                                                              \
     return n > 0 ? n : 1;                                                                                        \
   }
   if (v.kind == KIND_WIN_F32) {

@@ -39,6 +39,9 @@ struct Variant {
   int rowcap;  // LDS row capacity (f32: elements, u8: bytes)
   int nbuf;    // LDS buffers: 1 = synchronous staging, 2 = asynchronous double buffering
   int id;      // index in the variant list
+  // f32: 0 = one register window, 1 = two (pipelined); u8: 0 = one LDS copy per row, int32 sums;
+  // 1 = four byte-shifted copies, packed 16-bit sums (at most 257 input rows); 2 = as 1, flushed to int32
+  int mode = 0;
   int st() const { return kind == KIND_WIN_F32 ? 64 * tp : 256 * tp; }
   int dt() const { return nwave * dpw; }
   // ints per wave-table entry: f32 {win_start, nl, one offset per row} padded to 4/8/16; u8 packed u16 offsets
@@ -74,6 +77,7 @@ struct TileArgs {
   int nout;                  // output samples per row
   int n_time_tiles;
   int n_row_tiles;
+  int tiles_per_block;       // time tiles walked by one block (uint8 double-buffered kernels)
   const int32_t* blk;
   const int32_t* wav;
   const float* w_in;         // per input-row weight or null
@@ -121,6 +125,7 @@ dedisp_status hip_fail(hipError_t e, const char* what);
 // The plan object.
 struct dedisp_plan_s {
   int device = 0;
+  int ncu = 256;                    // compute units of the device
   int nchan = 0, ndm = 0, max_delay = 0;
   double tsamp = 0;
   std::vector<double> freq, dm;

@@ -67,6 +67,10 @@ typedef std::function<int(int, int)> DelayFn;
 static bool build_tables(const Variant& v, int rows_out, int rows_in, const DelayFn& delay, std::vector<int32_t>& blk,
                          std::vector<int32_t>& wav, int& n_row_tiles, int& max_stage, std::string& why) {
   const int DT = v.dt(), DPW = v.dpw, NW = v.nwave, WI = v.wav_ints();
+  if (v.kind == KIND_TILE_U8 && v.mode == 1 && rows_in > 257) {
+    why = "more than 257 input rows overflow its 16-bit packed sums";
+    return false;
+  }
   n_row_tiles = (rows_out + DT - 1) / DT;
   const int n_wave_tiles = n_row_tiles * NW;
   blk.assign((size_t)n_row_tiles * rows_in * 2, 0);
@@ -93,7 +97,8 @@ static bool build_tables(const Variant& v, int rows_out, int rows_in, const Dela
               return false;
             }
             maxo = std::max(maxo, o);
-            e[2 + j] = o;
+            // pipelined variants sum row c from register bank c & 1
+            e[2 + j] = o + ((v.mode == 1 && (c & 1)) ? v.nwin : 0);
           }
           const int nl = std::max(v.tp / 4 + 1, (v.tp + maxo + 3) / 4);
           e[0] = ws;
@@ -255,6 +260,8 @@ dedisp_status dedisp_plan_create(dedisp_plan* plan, int32_t nchan, const double*
   }
   p->adj_pad = (p->max_delay + 3) & ~3;
   hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&p->ncu, hipDeviceAttributeMultiprocessorCount, p->device);
+  if (e == hipSuccess && p->ncu < 1) p->ncu = 1;
   if (e == hipSuccess) e = hipMalloc(&p->d_delay, p->delay.size() * sizeof(int32_t));
   if (e == hipSuccess)
     e = hipMemcpy(p->d_delay, p->delay.data(), p->delay.size() * sizeof(int32_t), hipMemcpyHostToDevice);
@@ -411,6 +418,9 @@ dedisp_status dedisp_execute(dedisp_plan p, int32_t nbeam, int32_t nsamp, const 
   a.nout = nsamp;
   a.n_time_tiles = (nsamp + v.st() - 1) / v.st();
   a.n_row_tiles = t->n_row_tiles;
+  // blocks that walk several time tiles: about six per CU in total
+  a.tiles_per_block = (int)std::max<int64_t>(
+      1, std::min<int64_t>(a.n_time_tiles, (int64_t)a.n_time_tiles * a.n_row_tiles * nbeam / (6 * p->ncu)));
   a.blk = t->d_blk;
   a.wav = t->d_wav;
   a.w_in = d_w;

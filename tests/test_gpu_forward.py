@@ -197,6 +197,40 @@ def test_u8_ragged():
             assert np.array_equal(out.cpu().numpy(), ref), (nc, nd, ns, v)
 
 
+@pytest.mark.parametrize("nc", [257, 258, 600])
+def test_u8_many_rows_packed_sums(nc):
+    """Sums past 16 bits: 257 rows of 255 is the largest sum a packed 16-bit
+    lane holds (65535); 258 and 600 rows need the int32 flush of the wide
+    byte-shifted variants (the narrow ones must refuse such plans)."""
+    dd = _dd()
+    rng = np.random.default_rng(nc)
+    f = 1270.0 + (np.arange(nc) + 0.5) * 300.0 / nc
+    dms = np.arange(24) * 0.25
+    delta = oracle.delay_table(f, 50e-6, dms)
+    ns = 1500
+    nin = ns + int(delta.max())
+    x = np.full((1, nc, nin), 255, np.uint8)
+    x[:, ::3] = rng.integers(200, 256, size=x[:, ::3].shape).astype(np.uint8)
+    ref = oracle.forward_u8(x, delta, ns)
+    plan = dd.Plan(f, 50e-6, dms)
+    names = dd.variant_names("u8")
+    vs = _variants(plan, "u8")
+    narrow = [i for i, n in enumerate(names) if n.startswith("u8s_") and not n.endswith("_wide")]
+    wide = [i for i, n in enumerate(names) if n.endswith("_wide")]
+    assert wide and all(v in vs for v in wide)
+    if nc > 257:
+        assert not any(v in vs for v in narrow)
+    else:
+        assert all(v in vs for v in narrow)
+    xg = _to_gpu(x, pad_extra=16)
+    for v in vs:
+        _note(f"u8 {nc} rows variant {v}")
+        plan.set_variant(v, "u8")
+        out = dd.dedisperse(xg, plan, nsamp=ns)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref), (nc, v)
+
+
 def _sample_points(rng, nb, nd, ns, n):
     pb = rng.integers(0, nb, n)
     pd = rng.integers(0, nd, n)
