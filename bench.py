@@ -39,9 +39,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batched", choices=["batched", "apertif", "lofar", "diff"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "apertif", "lofar", "diff", "copy"],
+                    help="copy: a plain 1 GiB device copy, the reference for HBM byte counters")
     ap.add_argument("--no-tune", action="store_true", help="use default variants (no autotuning)")
-    ap.add_argument("--variant", type=int, default=None, help="force a kernel variant (single-beam workloads)")
+    ap.add_argument("--variant", type=int, default=None, help="force a kernel variant (no autotuning)")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-beam loop")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
@@ -128,6 +129,48 @@ def cpu_baseline(beam, target_s):
     }
 
 
+def kernel_sources_hash():
+    """Hash of the kernel sources: stored byte counters apply only to the kernels they were taken on."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("engine.hip", "win_asm.inc"):
+        with open(os.path.join(ROOT, "paper_1601_01165_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload, variant):
+    """HBM bytes per launch measured with rocprofv3 counters (FETCH_SIZE +
+    WRITE_SIZE, scaled by the same counters of a plain copy of known size),
+    from the summary committed under profiles/; None if there is none for
+    this workload and variant or the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    want = kernel_sources_hash()
+    for ln in open(path):
+        if not ln.startswith("traffic "):
+            continue
+        kv = dict(tok.split("=", 1) for tok in ln.split()[1:])
+        if kv.get("workload") == workload and kv.get("variant") == variant and kv.get("sources") == want:
+            return float(kv["bytes_per_launch"])
+    return None
+
+
+def copy_calibration(args, torch, sync):
+    """A plain device copy of known size: its HBM byte counters scale the
+    dedispersion kernels' counters to bytes."""
+    n = 1 << 28  # float32 elements: 1 GiB read and 1 GiB written per launch
+    x = torch.ones(n, device="cuda")
+    y = torch.empty_like(x)
+    ms, launch_ms, _ = time_steps(lambda: y.copy_(x), args.steps, args.warmup, sync)
+    kms = float(np.mean(launch_ms))
+    print(json.dumps({"metric": "device copy", "value": 2 * 4 * n / (kms / 1e3) / 1e9, "unit": "GB/s",
+                      "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n, "ms_per_step": ms,
+                      "kernel_ms": kms, "steps": args.steps, "warmup": args.warmup}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -145,6 +188,9 @@ def main():
     sync = torch.cuda.synchronize
 
     wl = args.workload
+    if wl == "copy":
+        copy_calibration(args, torch, sync)
+        return
     extra = {}
     if wl in ("batched", "apertif", "diff"):
         k = {"batched": 3, "apertif": 1, "diff": 4}[wl]
@@ -191,11 +237,14 @@ def main():
 
     plain = None
     if wl == "batched":
-        batch = dd.Batch(plans, xs, outs, tune=not args.no_tune)
-        log("batch created (variant chosen)")
+        batch = dd.Batch(plans, xs, outs, tune=not args.no_tune and args.variant is None)
+        if args.variant is not None:
+            batch.set_variant(args.variant)
+        variant_name = dd.variant_names("f32")[batch.variant]
+        log(f"batch created: variant {batch.variant} {variant_name}")
         step = batch.execute
         if not args.no_plain:
-            if not args.no_tune:
+            if not args.no_tune and args.variant is None:
                 for i, (p, b) in enumerate(zip(plans, beams)):
                     p.autotune(1, b.nsamp, "f32")
                     if i % 64 == 63:
@@ -216,7 +265,11 @@ def main():
 
         def step():
             dd.dedisperse(x, p, nsamp=b.nsamp, out=o)
-        kernel_name = "u8_kernel" if b.dtype == "u8" else "win_kernel"
+        dt = "u8" if b.dtype == "u8" else "f32"
+        vi = p.variant(dt)
+        variant_name = dd.variant_names(dt)[vi] if vi >= 0 else "direct"
+        kernel_name = ("direct_u8_kernel" if dt == "u8" else "direct_f32_kernel") if vi < 0 else \
+            ("u8s_kernel" if variant_name.startswith("u8s_") else "u8_kernel" if dt == "u8" else "win_kernel")
     else:  # diff: forward + adjoint with the weight gradient over all beams
         w = torch.ones(beams[0].nchan, device=dev)
         p0 = plans[0]
@@ -234,6 +287,7 @@ def main():
             dd.dedisperse(xb, p0, w, nsamp=beams[0].nsamp, out=ob)
             dd.adjoint(g, p0, nin, w, xb)
         kernel_name = "win_kernel (forward + adjoint)"
+        variant_name = f"{dd.variant_names('f32')[p0.variant('f32')]} (forward)"
 
     log("timing")
     ms, launch_ms, wall = time_steps(step, args.steps, args.warmup, sync)
@@ -250,6 +304,7 @@ def main():
         "frac": achieved / ADD_PEAK,
         "traffic": None,
         "kernel": kernel_name,
+        "variant": variant_name,
         "kernel_ms": kern_ms,
         "note": "one FP32 add per (channel, DM trial, sample), the paper's flop count; peak = 157.3/2",
     }
@@ -257,6 +312,8 @@ def main():
         roof.update({"bound": "hbm", "achieved": algo_bytes / (kern_ms / 1e3) / 1e9, "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": algo_bytes / (kern_ms / 1e3) / HBM_PEAK,
                      "note": "algorithmic bytes: input once + int32 output + delay table"})
+    roof["traffic"] = stored_traffic(wl, variant_name)
+    roof["algorithmic_bytes"] = algo_bytes
     line = {
         "metric": METRIC,
         "value": value,

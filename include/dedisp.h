@@ -179,6 +179,17 @@ dedisp_status dedisp_execute_batched(dedisp_batch batch, void* stream);
  * (the plain per-beam launch loop the batched launch is compared with). */
 dedisp_status dedisp_execute_per_beam(dedisp_batch batch, void* stream);
 
+/* Switch the batch to tiled variant `variant` (an index of
+ * dedisp_variant_name(DEDISP_F32, .)): rebuilds the work table and drops the
+ * captured graph (the next dedisp_execute_batched captures again).  Waits
+ * for the device first.  DEDISP_E_INVALID for an index out of range,
+ * DEDISP_E_UNTUNED if the variant does not fit some beam (the batch keeps its
+ * variant then).  Allocates; not for use under graph capture. */
+dedisp_status dedisp_batch_set_variant(dedisp_batch batch, int32_t variant);
+
+/* The tiled variant the batch runs (-1 for a NULL batch). */
+int32_t dedisp_batch_variant(dedisp_batch batch);
+
 dedisp_status dedisp_batch_destroy(dedisp_batch batch);
 
 /* ------------------------------------------------------------------------ */

@@ -298,6 +298,15 @@ class Batch:
     def execute_per_beam(self):
         check(lib().dedisp_execute_per_beam(self._h, _stream()), "execute_per_beam")
 
+    @property
+    def variant(self) -> int:
+        """Index of the FP32 tiled variant the batch runs."""
+        return int(lib().dedisp_batch_variant(self._h))
+
+    def set_variant(self, i: int):
+        """Run the batch with FP32 tiled variant i (rebuilds its work table)."""
+        check(lib().dedisp_batch_set_variant(self._h, int(i)), "batch_set_variant")
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().dedisp_batch_destroy(self._h)

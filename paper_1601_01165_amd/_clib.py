@@ -32,6 +32,8 @@ SIGNATURES = {
     "dedisp_batch_create": (i32, [ctypes.POINTER(vp), i32, vp, vp, vp, vp, vp, vp, vp, i32]),
     "dedisp_execute_batched": (i32, [vp, vp]),
     "dedisp_execute_per_beam": (i32, [vp, vp]),
+    "dedisp_batch_set_variant": (i32, [vp, i32]),
+    "dedisp_batch_variant": (i32, [vp]),
     "dedisp_batch_destroy": (i32, [vp]),
     "dedisp_autotune": (i32, [vp, i32, i32, i32, cp]),
     "dedisp_autotune_times": (i32, [vp, i32, vp, i32]),

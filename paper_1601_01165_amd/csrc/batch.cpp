@@ -13,10 +13,6 @@
 
 namespace dd {
 dedisp_status ensure_tables(dedisp_plan p, int dir, int vi, Tables** out);
-int autotune_batch_variant(const std::vector<dedisp_plan>& plans, const std::vector<int32_t>& nsamp,
-                           const std::vector<const float*>& d_in, const std::vector<int64_t>& in_stride,
-                           const std::vector<const float*>& d_w, const std::vector<float*>& d_out,
-                           const std::vector<int64_t>& out_stride);
 }  // namespace dd
 
 using namespace dd;
@@ -33,6 +29,8 @@ struct dedisp_batch_s {
   std::vector<int64_t> out_stride;
   BeamDesc* d_beams = nullptr;
   int32_t* d_order = nullptr;
+  int32_t* d_qoff = nullptr;  // kNumXcd + 1 queue offsets into d_order (in pairs)
+  int nqueue = 1;             // queues in use: 1 (one global order) or kNumXcd (one per XCD)
   int* d_counter = nullptr;
   int64_t ntiles = 0;
   int grid = 0;
@@ -41,14 +39,12 @@ struct dedisp_batch_s {
   hipGraphExec_t exec = nullptr;
 };
 
+static void drop_work(dedisp_batch b);
+
 static void batch_free(dedisp_batch b) {
   if (!b) return;
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
+  drop_work(b);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-  if (b->d_beams) (void)hipFree(b->d_beams);
-  if (b->d_order) (void)hipFree(b->d_order);
-  if (b->d_counter) (void)hipFree(b->d_counter);
   delete b;
 }
 
@@ -68,7 +64,25 @@ static dedisp_status check_beam(int i, dedisp_plan p, int32_t ns, const float* i
   return DEDISP_OK;
 }
 
-// Build the beam descriptors and the work table for variant vi.
+// Free the work table, descriptors and captured graph of the current variant.
+static void drop_work(dedisp_batch b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->d_beams) (void)hipFree(b->d_beams);
+  if (b->d_order) (void)hipFree(b->d_order);
+  if (b->d_qoff) (void)hipFree(b->d_qoff);
+  if (b->d_counter) (void)hipFree(b->d_counter);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->d_beams = nullptr;
+  b->d_order = nullptr;
+  b->d_qoff = nullptr;
+  b->d_counter = nullptr;
+  b->variant = -1;
+}
+
+// Build the beam descriptors and the work table for variant vi, dealt over
+// b->nqueue queues.
 static dedisp_status build_work(dedisp_batch b, int vi) {
   const Variant& v = variants_f32()[vi];
   std::vector<BeamDesc> beams(b->nbeam);
@@ -106,27 +120,40 @@ static dedisp_status build_work(dedisp_batch b, int vi) {
   for (int i = 0; i < b->nbeam; ++i)
     if ((b->d_w[i] != nullptr) != (b->d_w[0] != nullptr))
       return fail(DEDISP_E_INVALID, "weights must be given for all beams or none");
-  // Work table: (beam, local tile) pairs, beams with the costliest tiles first;
-  // within a beam, time-major with output-row tiles fastest.
+  // Work table: (beam, local tile) pairs, beams with the costliest tiles first.
+  // Each (beam, time tile) group, with its row tiles in order, goes to one
+  // queue; groups are dealt round-robin over the nqueue queues in use (the
+  // others stay empty).
   std::vector<int> ord(b->nbeam);
   std::iota(ord.begin(), ord.end(), 0);
   std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-  std::vector<int32_t> order;
-  order.reserve((size_t)total * 2);
+  std::vector<std::vector<int32_t>> qs(kNumXcd);
+  int64_t g = 0;
   for (int i : ord) {
-    const int64_t n = (int64_t)beams[i].a.n_time_tiles * beams[i].a.n_row_tiles;
-    for (int64_t k = 0; k < n; ++k) {
-      order.push_back(i);
-      order.push_back((int32_t)k);
+    const TileArgs& a = beams[i].a;
+    for (int tt = 0; tt < a.n_time_tiles; ++tt, ++g) {
+      std::vector<int32_t>& q = qs[g % b->nqueue];
+      for (int rt = 0; rt < a.n_row_tiles; ++rt) {
+        q.push_back(i);
+        q.push_back(tt * a.n_row_tiles + rt);
+      }
     }
+  }
+  std::vector<int32_t> order, qoff(kNumXcd + 1, 0);
+  order.reserve((size_t)total * 2);
+  for (int q = 0; q < kNumXcd; ++q) {
+    order.insert(order.end(), qs[q].begin(), qs[q].end());
+    qoff[q + 1] = (int32_t)(order.size() / 2);
   }
   b->ntiles = total;
   hipError_t e = hipMalloc(&b->d_beams, sizeof(BeamDesc) * b->nbeam);
   if (e == hipSuccess) e = hipMalloc(&b->d_order, sizeof(int32_t) * order.size());
-  if (e == hipSuccess) e = hipMalloc(&b->d_counter, sizeof(int) * 64);
+  if (e == hipSuccess) e = hipMalloc(&b->d_qoff, sizeof(int32_t) * qoff.size());
+  if (e == hipSuccess) e = hipMalloc(&b->d_counter, sizeof(int) * kNumXcd * kCounterStride);
   if (e == hipSuccess) e = hipMemcpy(b->d_beams, beams.data(), sizeof(BeamDesc) * b->nbeam, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->d_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemset(b->d_counter, 0, sizeof(int) * 64);
+  if (e == hipSuccess) e = hipMemcpy(b->d_qoff, qoff.data(), sizeof(int32_t) * qoff.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(b->d_counter, 0, sizeof(int) * kNumXcd * kCounterStride);
   if (e != hipSuccess) return hip_fail(e, "uploading the batch work table");
   int dev = 0, ncu = 0;
   e = hipGetDevice(&dev);
@@ -135,6 +162,70 @@ static dedisp_status build_work(dedisp_batch b, int vi) {
   b->grid = ncu * batched_blocks_per_cu(v);
   b->variant = vi;
   return DEDISP_OK;
+}
+
+// The batch's auto-tuning (Sections 2.2 and 4.1, applied to the whole
+// batch): time the persistent launch of every variant that fits every beam
+// on the batch's own buffers (their outputs are overwritten by the real run)
+// and return the fastest, or -1; then time the winner with one queue per XCD
+// and keep that split if it is faster.  Leaves the batch without a work
+// table.
+static int tune_batch(dedisp_batch b) {
+  const std::vector<Variant>& vs = variants_f32();
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return -1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    (void)hipStreamDestroy(s);
+    return -1;
+  }
+  int best = -1;
+  float best_ms = 1e30f;
+  for (int vi = 0; vi < (int)vs.size(); ++vi) {
+    bool ok = true;
+    for (int i = 0; i < b->nbeam && ok; ++i) ok = ensure_tables(b->plans[i], 0, vi, nullptr) == DEDISP_OK;
+    if (!ok) continue;
+    drop_work(b);
+    b->nqueue = 1;
+    if (build_work(b, vi) != DEDISP_OK) continue;
+    const bool weighted = b->d_w[0] != nullptr;
+    const float ms = median_ms(
+        [&]() {
+          const hipError_t r = launch_zero_counter(b->d_counter, s);
+          return r == hipSuccess
+                     ? launch_batched(vs[vi], b->d_beams, weighted, b->d_order, b->d_qoff, b->d_counter, b->grid, s)
+                     : r;
+        },
+        s, 2, e0, e1);
+    if (ms > 0 && ms < best_ms) {
+      best_ms = ms;
+      best = vi;
+    }
+  }
+  // the best variant with one queue per XCD as well
+  if (best >= 0) {
+    drop_work(b);
+    b->nqueue = kNumXcd;
+    float ms = -1.f;
+    if (build_work(b, best) == DEDISP_OK) {
+      const bool weighted = b->d_w[0] != nullptr;
+      ms = median_ms(
+          [&]() {
+            const hipError_t r = launch_zero_counter(b->d_counter, s);
+            return r == hipSuccess ? launch_batched(vs[best], b->d_beams, weighted, b->d_order, b->d_qoff,
+                                                    b->d_counter, b->grid, s)
+                                   : r;
+          },
+          s, 2, e0, e1);
+    }
+    if (!(ms > 0 && ms < best_ms)) b->nqueue = 1;
+  }
+  drop_work(b);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  return best;
 }
 
 extern "C" {
@@ -167,7 +258,7 @@ dedisp_status dedisp_batch_create(dedisp_batch* out, int32_t nbeam, const dedisp
   }
   // Variant: the tuned choice, or the first default that fits every beam.
   int vi = -1;
-  if (tune) vi = autotune_batch_variant(b->plans, b->nsamp, b->d_in, b->in_stride, b->d_w, b->d_out, b->out_stride);
+  if (tune) vi = tune_batch(b);
   if (vi < 0) {
     static const int pref[] = {0, 1, 2, 4, 3, 5};
     for (int k : pref) {
@@ -199,6 +290,7 @@ dedisp_status dedisp_batch_create(dedisp_batch* out, int32_t nbeam, const dedisp
 
 dedisp_status dedisp_execute_batched(dedisp_batch b, void* stream) {
   if (!b) return fail(DEDISP_E_INVALID, "batch is NULL");
+  if (b->variant < 0) return fail(DEDISP_E_INVALID, "batch has no work table (a variant change failed)");
   const Variant& v = variants_f32()[b->variant];
   hipError_t e;
   if (!b->exec) {
@@ -206,7 +298,7 @@ dedisp_status dedisp_execute_batched(dedisp_batch b, void* stream) {
     e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "beginning graph capture");
     hipError_t e1 = launch_zero_counter(b->d_counter, b->cap_stream);
-    hipError_t e2 = launch_batched(v, b->d_beams, b->d_w[0] != nullptr, b->d_order, b->ntiles, b->d_counter,
+    hipError_t e2 = launch_batched(v, b->d_beams, b->d_w[0] != nullptr, b->d_order, b->d_qoff, b->d_counter,
                                    b->grid, b->cap_stream);
     e = hipStreamEndCapture(b->cap_stream, &b->graph);
     if (e1 != hipSuccess) return hip_fail(e1, "capturing the counter reset");
@@ -231,6 +323,22 @@ dedisp_status dedisp_execute_per_beam(dedisp_batch b, void* stream) {
   }
   return DEDISP_OK;
 }
+
+dedisp_status dedisp_batch_set_variant(dedisp_batch b, int32_t variant) {
+  if (!b) return fail(DEDISP_E_INVALID, "batch is NULL");
+  if (variant < 0 || variant >= (int32_t)variants_f32().size())
+    return fail(DEDISP_E_INVALID, "variant index out of range");
+  for (int i = 0; i < b->nbeam; ++i) {
+    dedisp_status st = ensure_tables(b->plans[i], 0, variant, nullptr);
+    if (st != DEDISP_OK) return st;
+  }
+  const hipError_t e = hipDeviceSynchronize();  // no replay of the old graph is in flight
+  if (e != hipSuccess) return hip_fail(e, "synchronizing before a variant change");
+  drop_work(b);
+  return build_work(b, variant);
+}
+
+int32_t dedisp_batch_variant(dedisp_batch b) { return b ? b->variant : -1; }
 
 dedisp_status dedisp_batch_destroy(dedisp_batch b) {
   batch_free(b);

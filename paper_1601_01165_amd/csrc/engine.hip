@@ -25,6 +25,8 @@
 //   * accumulation order per output is ascending input row with one rounding
 //     per term, the order of Algorithm 1, so the FP32 results are those of a
 //     sequential FP32 loop.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace dd {
@@ -399,32 +401,41 @@ __global__ __launch_bounds__(64 * NWAVE) void win_kernel(TileArgs a) {
                                                                        blockIdx.y, lds4);
 }
 
-// Persistent form for batches of beams: blocks take tiles from a work table
-// (ordered by decreasing cost) through an atomic counter until it runs out.
+// Persistent form for batches of beams.  The work table is split into one
+// queue per XCD (all row tiles of a (beam, time tile) in the same queue, so
+// the blocks sharing that input window share that XCD's L2).  Blocks are
+// dispatched round-robin over the XCDs, so block i drains queue i % NXCD
+// first and then helps the others, in order, until every queue is empty.
 // Every beam shares the variant; per-beam pointers and tables come from its
-// descriptor.  The counter is cleared by a separate kernel before each launch.
+// descriptor.  The counters (one per queue, 128 bytes apart) are cleared by a
+// separate kernel before each launch.
 template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool PIPE, bool WEIGHTED>
 __global__ __launch_bounds__(64 * NWAVE) void win_persistent(const BeamDesc* __restrict__ beams,
-                                                             const int32_t* __restrict__ order, int64_t ntiles,
-                                                             int* counter) {
+                                                             const int32_t* __restrict__ order,
+                                                             const int32_t* __restrict__ qoff, int* counters) {
   __shared__ float4 lds4[NBUF * CC * ROWCAP / 4];
   __shared__ int s_tile;
-  for (;;) {
-    __syncthreads();  // everyone is done with s_tile and the LDS rows
-    if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
-    __syncthreads();
-    const int64_t k = s_tile;
-    if (k >= ntiles) break;
-    const int b = order[2 * k];
-    const int local = order[2 * k + 1];
-    const TileArgs& a = beams[b].a;
-    const int tt = local / a.n_row_tiles, rt = local % a.n_row_tiles;
-    win_any<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, PIPE, WEIGHTED, false>(a, tt, rt, 0, lds4);
+  const int home = blockIdx.x % kNumXcd;
+  for (int qi = 0; qi < kNumXcd; ++qi) {
+    const int q = (home + qi) % kNumXcd;
+    const int q0 = qoff[q], n = qoff[q + 1] - q0;
+    for (;;) {
+      __syncthreads();  // everyone is done with s_tile and the LDS rows
+      if (threadIdx.x == 0) s_tile = atomicAdd(counters + q * kCounterStride, 1);
+      __syncthreads();
+      const int k = s_tile;
+      if (k >= n) break;
+      const int b = order[2 * (q0 + k)];
+      const int local = order[2 * (q0 + k) + 1];
+      const TileArgs& a = beams[b].a;
+      const int tt = local / a.n_row_tiles, rt = local % a.n_row_tiles;
+      win_any<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, PIPE, WEIGHTED, false>(a, tt, rt, 0, lds4);
+    }
   }
 }
 
 __global__ void zero_counter_kernel(int* c) {
-  if (threadIdx.x == 0) c[0] = 0;
+  if (threadIdx.x < kNumXcd) c[threadIdx.x * kCounterStride] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1027,16 +1038,16 @@ hipError_t launch_tiled(const Variant& v, const TileArgs& a, int nbeam, bool adj
 }
 
 hipError_t launch_batched(const Variant& v, const BeamDesc* d_beams, bool weighted, const int32_t* d_order,
-                          int64_t ntiles, int* d_counter, int grid, hipStream_t s) {
+                          const int32_t* d_qoff, int* d_counter, int grid, hipStream_t s) {
   const dim3 block(64 * v.nwave);
 #define LAUNCH_P(ID, TP, DPW, NW, NWIN, CC, RC, NB, PIPE)                                                        \
   if (v.id == ID) {                                                                                              \
     if (weighted)                                                                                                \
       hipLaunchKernelGGL((win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, PIPE, true>), dim3(grid), block, 0, s,  \
-                         d_beams, d_order, ntiles, d_counter);                                                   \
+                         d_beams, d_order, d_qoff, d_counter);                                                   \
     else                                                                                                         \
       hipLaunchKernelGGL((win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, PIPE, false>), dim3(grid), block, 0, s, \
-                         d_beams, d_order, ntiles, d_counter);                                                   \
+                         d_beams, d_order, d_qoff, d_counter);                                                   \
     return hipGetLastError();                                                                                    \
   }
   if (v.kind == KIND_WIN_F32) {
@@ -1060,6 +1071,31 @@ int batched_blocks_per_cu(const Variant& v) {
   }
 #undef OCC_P
   return 1;
+}
+
+// 32-bit integer hash (a murmur3-style finaliser) of the word index.
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+__global__ void fill_random_kernel(uint32_t* p, size_t nwords, bool f32, uint32_t seed) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nwords; i += (size_t)gridDim.x * blockDim.x) {
+    const uint32_t h = hash32((uint32_t)i * 2654435761u + seed);
+    p[i] = f32 ? __float_as_uint((float)(h >> 8) * (1.f / 8388608.f) - 1.f) : h;
+  }
+}
+
+hipError_t launch_fill_random(void* p, size_t nbytes, bool f32, uint32_t seed, hipStream_t s) {
+  const size_t nwords = nbytes / 4;  // a tail of < 4 bytes keeps its contents
+  if (nwords == 0) return hipSuccess;
+  const size_t blocks = std::min<size_t>((nwords + 255) / 256, 65536);
+  hipLaunchKernelGGL(fill_random_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, nwords, f32, seed);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero_counter(int* d_counter, hipStream_t s) {

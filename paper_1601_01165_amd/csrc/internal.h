@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -111,10 +112,23 @@ hipError_t launch_direct_adjoint(const float* g, int64_t g_stride, int64_t g_bea
                                  int64_t gi_stride, int64_t gi_beam_stride, const float* x, int64_t x_stride,
                                  int64_t x_beam_stride, double* partial, int nbeam, hipStream_t s);
 hipError_t launch_reduce_gradw(const double* partial, int nparts, int nchan, float* grad_w, hipStream_t s);
+// Persistent launch over a work table of (beam, local tile) pairs split into
+// kNumXcd queues: queue q is order[2*qoff[q] .. 2*qoff[q+1]); d_counter holds
+// kNumXcd counters kCounterStride ints apart.
+constexpr int kNumXcd = 8;
+constexpr int kCounterStride = 32;
 hipError_t launch_batched(const Variant& v, const BeamDesc* d_beams, bool weighted, const int32_t* d_order,
-                          int64_t ntiles, int* d_counter, int grid, hipStream_t s);
+                          const int32_t* d_qoff, int* d_counter, int grid, hipStream_t s);
 hipError_t launch_zero_counter(int* d_counter, hipStream_t s);
 int batched_blocks_per_cu(const Variant& v);
+
+// Timing (tune.cpp): median of `reps` launches of fn after a warm-up launch,
+// -1 if a launch fails.
+float median_ms(const std::function<hipError_t()>& fn, hipStream_t s, int reps, hipEvent_t e0, hipEvent_t e1);
+
+// Fill nbytes of device memory with seeded pseudo-random data (f32: values in
+// [-1, 1); otherwise bytes), for timing on realistic inputs.
+hipError_t launch_fill_random(void* p, size_t nbytes, bool f32, uint32_t seed, hipStream_t s);
 
 // Errors (plan.cpp).
 dedisp_status fail(dedisp_status st, const std::string& msg);

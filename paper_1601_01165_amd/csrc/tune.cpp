@@ -97,8 +97,7 @@ static void cache_store(const char* path, const std::string& key, const std::str
 }
 
 // Median time in ms of `reps` launches of fn after one warm-up launch.
-template <typename F>
-static float time_ms(F fn, hipStream_t s, int reps, hipEvent_t e0, hipEvent_t e1) {
+float median_ms(const std::function<hipError_t()>& fn, hipStream_t s, int reps, hipEvent_t e0, hipEvent_t e1) {
   if (fn() != hipSuccess) return -1.f;
   std::vector<float> t;
   for (int r = 0; r < reps; ++r) {
@@ -121,98 +120,6 @@ static std::vector<float>& last_times(dedisp_plan p, dedisp_dtype t) {
     if (kv.first.first == p && kv.first.second == (int)t) return kv.second;
   store.push_back({{p, (int)t}, {}});
   return store.back().second;
-}
-
-int autotune_batch_variant(const std::vector<dedisp_plan>& plans, const std::vector<int32_t>& nsamp,
-                           const std::vector<const float*>& d_in, const std::vector<int64_t>& in_stride,
-                           const std::vector<const float*>& d_w, const std::vector<float*>& d_out,
-                           const std::vector<int64_t>& out_stride) {
-  // Time each variant that fits every beam as one persistent launch over the
-  // real buffers (outputs are overwritten by the real run later).
-  const std::vector<Variant>& vs = variants_f32();
-  const int nb = (int)plans.size();
-  hipStream_t s;
-  hipEvent_t e0, e1;
-  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return -1;
-  (void)hipEventCreate(&e0);
-  (void)hipEventCreate(&e1);
-  int best = -1;
-  float best_ms = 1e30f;
-  for (int vi = 0; vi < (int)vs.size(); ++vi) {
-    bool ok = true;
-    for (int i = 0; i < nb && ok; ++i) ok = ensure_tables(plans[i], 0, vi, nullptr) == DEDISP_OK;
-    if (!ok) continue;
-    dedisp_batch b = nullptr;
-    // Build a non-tuned batch pinned to this variant by temporarily making it
-    // the only fitting candidate is not possible through the C-ABI, so time
-    // the persistent kernel directly.
-    std::vector<BeamDesc> beams(nb);
-    std::vector<int32_t> order;
-    const Variant& v = vs[vi];
-    for (int i = 0; i < nb; ++i) {
-      Tables* t = nullptr;
-      ensure_tables(plans[i], 0, vi, &t);
-      TileArgs& a = beams[i].a;
-      a = TileArgs{};
-      a.in = d_in[i];
-      a.in_stride = in_stride[i];
-      a.in_hi = (int)in_stride[i];
-      a.rows_in = plans[i]->nchan;
-      a.rows_out = plans[i]->ndm;
-      a.nout = nsamp[i];
-      a.n_time_tiles = (nsamp[i] + v.st() - 1) / v.st();
-      a.n_row_tiles = t->n_row_tiles;
-      a.blk = t->d_blk;
-      a.wav = t->d_wav;
-      a.w_in = d_w[i];
-      a.out = d_out[i];
-      a.out_stride = out_stride[i];
-    }
-    std::vector<int> ord(nb);
-    for (int i = 0; i < nb; ++i) ord[i] = i;
-    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return plans[x]->nchan > plans[y]->nchan; });
-    for (int i : ord) {
-      const int n = beams[i].a.n_time_tiles * beams[i].a.n_row_tiles;
-      for (int k = 0; k < n; ++k) {
-        order.push_back(i);
-        order.push_back(k);
-      }
-    }
-    (void)b;
-    BeamDesc* d_beams = nullptr;
-    int32_t* d_order = nullptr;
-    int* d_counter = nullptr;
-    hipError_t e = hipMalloc(&d_beams, sizeof(BeamDesc) * nb);
-    if (e == hipSuccess) e = hipMalloc(&d_order, sizeof(int32_t) * order.size());
-    if (e == hipSuccess) e = hipMalloc(&d_counter, 256);
-    if (e == hipSuccess) e = hipMemcpy(d_beams, beams.data(), sizeof(BeamDesc) * nb, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(d_order, order.data(), sizeof(int32_t) * order.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) {
-      int dev = 0, ncu = 0;
-      (void)hipGetDevice(&dev);
-      (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-      const int grid = ncu * batched_blocks_per_cu(v);
-      const int64_t ntiles = (int64_t)order.size() / 2;
-      const bool weighted = d_w[0] != nullptr;
-      float ms = time_ms(
-          [&]() {
-            hipError_t r = launch_zero_counter(d_counter, s);
-            return r == hipSuccess ? launch_batched(v, d_beams, weighted, d_order, ntiles, d_counter, grid, s) : r;
-          },
-          s, 2, e0, e1);
-      if (ms > 0 && ms < best_ms) {
-        best_ms = ms;
-        best = vi;
-      }
-    }
-    if (d_beams) (void)hipFree(d_beams);
-    if (d_order) (void)hipFree(d_order);
-    if (d_counter) (void)hipFree(d_counter);
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipStreamDestroy(s);
-  return best;
 }
 
 }  // namespace dd
@@ -242,7 +149,9 @@ dedisp_status dedisp_autotune(dedisp_plan p, int32_t nbeam, int32_t nsamp, dedis
   void* d_out = nullptr;
   hipError_t e = hipMalloc(&d_in, (size_t)nbeam * p->nchan * in_stride * esz);
   if (e == hipSuccess) e = hipMalloc(&d_out, (size_t)nbeam * p->ndm * out_stride * 4);
-  if (e == hipSuccess) e = hipMemset(d_in, 0, (size_t)nbeam * p->nchan * in_stride * esz);
+  // noise-like input: the clock under load, and so the timings, depend on the data
+  if (e == hipSuccess) e = launch_fill_random(d_in, (size_t)nbeam * p->nchan * in_stride * esz, !u8, 1601u, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     if (d_in) (void)hipFree(d_in);
     return e == hipErrorOutOfMemory ? fail(DEDISP_E_NOMEM, "autotune scratch allocation failed")
@@ -261,7 +170,7 @@ dedisp_status dedisp_autotune(dedisp_plan p, int32_t nbeam, int32_t nsamp, dedis
   float best_ms = 1e30f;
   for (int vi = -1; vi < (int)vs.size(); ++vi) {
     if (dedisp_plan_set_variant(p, t, vi) != DEDISP_OK) continue;
-    float ms = time_ms(
+    float ms = median_ms(
         [&]() {
           return dedisp_execute(p, nbeam, nsamp, d_in, t, in_stride, nullptr, d_out, out_t, out_stride, s) == DEDISP_OK
                      ? hipSuccess

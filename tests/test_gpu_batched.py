@@ -136,3 +136,38 @@ def test_autotune_single_plan_and_cache(tmp_path):
     out = dd.dedisperse(xg, plan2, nsamp=b.nsamp)
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), oracle.forward_f32(x, delta, b.nsamp))
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_batched_every_variant(weighted):
+    """The persistent kernel of every FP32 variant that fits the beams (the
+    pipelined two-window ones included) against the oracle; a variant that
+    does not fit is refused and leaves the batch runnable."""
+    dd = _dd()
+    beams = _small_batch(5, seed=43)
+    plans, xs, outs, ref_in, deltas, ws = _setup(beams, weighted)
+    batch = dd.Batch(plans, xs, outs, weights=ws)
+    names = dd.variant_names("f32")
+    ran = 0
+    for v in range(len(names)):
+        try:
+            batch.set_variant(v)
+        except dd.DedispError:
+            _note(f"variant {v} {names[v]} does not fit")
+            continue
+        assert batch.variant == v
+        _note(f"batched variant {v} {names[v]} weighted={weighted}")
+        for o in outs:
+            o.fill_(float("nan"))
+        batch.execute()
+        torch.cuda.synchronize()
+        for i, b in enumerate(beams):
+            w = None if ws is None else ws[i].cpu().numpy()
+            ref = oracle.forward_f32(ref_in[i], deltas[i], b.nsamp, w)
+            assert np.array_equal(outs[i].cpu().numpy(), ref), (v, i)
+        ran += 1
+    assert ran >= len(names) // 2
+    with pytest.raises(dd.DedispError):
+        batch.set_variant(len(names))
+    batch.execute()
+    torch.cuda.synchronize()
