@@ -269,15 +269,23 @@ __device__ __forceinline__ void win_tile(const TileArgs& a, int tt, int rt, int 
   for (int q = 0; q < NACC; ++q) acc[q] = (v16f)(0.f);
 
   // The wave's table entry (and weight) of the current input row live in
-  // SGPRs; each step fetches the next row's with scalar loads.
+  // SGPRs; each step fetches the next row's through buffer resources (reads
+  // past the last row return zero), advancing the byte offsets itself.
   typedef typename EntT<DPW>::type E;
-  E cur = sload_entry_t<E>(wav);
-  float wcur = WEIGHTED ? sload_f32(w_in) : 0.f;
+  const __amdgpu_buffer_rsrc_t trs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)wav, (short)0, a.rows_in * WI * 4, 0x00020000);
+  const __amdgpu_buffer_rsrc_t wrs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)w_in, (short)0, WEIGHTED ? a.rows_in * 4 : 0, 0x00020000);
+  uint32_t toff = WI * 4, woff = 4;
+  E ea = sload_entry_t<E>(wav), eb;
+  float wa = WEIGHTED ? sload_f32(w_in) : 0.f, wb = 0.f;
   const int npass = (a.rows_in + CC - 1) / CC;
   if (NBUF == 2) {
     __syncthreads();  // a previous tile of this block is done with the LDS rows
     stage_f32_async<NWAVE, ROWCAP>(lds4, in, a, blk, 0, min(CC, a.rows_in), t0);
   }
+  // LDS byte address of this lane's window in row slot 0 of buffer 0
+  const uint32_t lane_base = lds_base + (uint32_t)(lane * TP * 4);
   for (int p = 0; p < npass; ++p) {
     const int c0 = p * CC;
     const int ncc = min(CC, a.rows_in - c0);
@@ -294,111 +302,33 @@ __device__ __forceinline__ void win_tile(const TileArgs& a, int tt, int rt, int 
         stage_f32_async<NWAVE, ROWCAP>(lds4 + ((p + 1) & 1) * CC * (ROWCAP / 4), in, a, blk, c0 + CC,
                                        min(CC, a.rows_in - c0 - CC), t0);
     }
-    for (int cl = 0; cl < ncc; ++cl) {
-      const int cn = min(c0 + cl + 1, a.rows_in - 1);
-      const uint32_t addr = lds_base + (uint32_t)(((bufrow + cl) * ROWCAP + cur[0] + lane * TP) * 4);
-      E nxt;
-      float wn = 0.f;
-      win_step<TP, DPW, NWIN, WEIGHTED>(acc, addr, cur, wav + (size_t)cn * WI, nxt, wcur,
-                                        WEIGHTED ? w_in + cn : nullptr, wn);
-      cur = nxt;
-      wcur = wn;
+    // two rows per iteration with the entry registers swapping roles, so the
+    // next row's entry needs no copy
+    uint32_t row = lane_base + (uint32_t)(bufrow * ROWCAP * 4);
+    int cl = 0;
+    for (; cl + 1 < ncc; cl += 2) {
+      win_step<TP, DPW, NWIN, WEIGHTED>(acc, row + (uint32_t)ea[0] * 4u, ea, eb, trs, toff, wa, wb, wrs, woff);
+      row += ROWCAP * 4;
+      win_step<TP, DPW, NWIN, WEIGHTED>(acc, row + (uint32_t)eb[0] * 4u, eb, ea, trs, toff, wb, wa, wrs, woff);
+      row += ROWCAP * 4;
+    }
+    if (cl < ncc) {
+      win_step<TP, DPW, NWIN, WEIGHTED>(acc, row + (uint32_t)ea[0] * 4u, ea, eb, trs, toff, wa, wb, wrs, woff);
+      ea = eb;
+      wa = wb;
     }
   }
 
   win_store<TP, DPW, NWAVE, ADJ>(a, acc, tt, rt, beam);
 }
 
-// Pipelined form: two register windows.  The step of input row c loads the
-// window of row c + 1 into one bank while it sums row c from the other, so
-// the LDS latency hides behind the adds.  The rows of pass p + 1 must have
-// landed before the last step of pass p (it loads the first window of pass
-// p + 1); by then every wave has finished reading pass p's rows, so pass p + 2
-// is staged into pass p's buffer right after that barrier.
-template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, bool WEIGHTED, bool ADJ>
-__device__ __forceinline__ void win_tile_pipe(const TileArgs& a, int tt, int rt, int beam, float4* lds4) {
-  constexpr int ST = 64 * TP;
-  constexpr int NACC = TP * DPW / 16;
-  constexpr int WI = EntT<DPW>::ints;
-  constexpr int BUF = CC * (ROWCAP / 4);  // float4 per LDS buffer
-  typedef typename EntT<DPW>::type E;
-  const int t0 = tt * ST;
-  const int wave = wave_id(), lane = threadIdx.x & 63;
-  const int wt = rt * NWAVE + wave;
-  const int R = a.rows_in;
-  const int npass = (R + CC - 1) / CC;
-  const float* in = static_cast<const float*>(a.in) + (int64_t)beam * a.in_beam_stride;
-  const int32_t* __restrict__ blk = uniform_ptr(a.blk + (size_t)rt * R * 2);
-  const int32_t* __restrict__ wav = uniform_ptr(a.wav + (size_t)wt * R * WI);
-  const float* w_in = WEIGHTED ? uniform_ptr(a.w_in) : nullptr;
-  const uint32_t lane_base = (uint32_t)(uintptr_t)(LDS_AS float4*)(lds4) + (uint32_t)(lane * TP * 4);
-
-  v16f acc[NACC];
-#pragma unroll
-  for (int q = 0; q < NACC; ++q) acc[q] = (v16f)(0.f);
-  BankT<NWIN> ba = {}, bb = {};
-
-  // LDS byte address of this lane's window of row c starting at element ws
-  auto row_addr = [&](int c, int ws) -> uint32_t {
-    const int buf = (c / CC) & 1;
-    return lane_base + (uint32_t)(((buf * CC + c % CC) * ROWCAP + ws) * 4);
-  };
-
-  // entries (and weights) of rows c, c + 1; each step fetches row c + 2's
-  E e0 = sload_entry_t<E>(wav);
-  E e1 = sload_entry_t<E>(wav + (size_t)min(1, R - 1) * WI);
-  float w0 = WEIGHTED ? sload_f32(w_in) : 0.f;
-  float w1 = WEIGHTED ? sload_f32(w_in + min(1, R - 1)) : 0.f;
-
-  __syncthreads();  // a previous tile of this block is done with the LDS rows
-  stage_f32_async<NWAVE, ROWCAP>(lds4, in, a, blk, 0, min(CC, R), t0);
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  fix_tail_async<NWAVE, ROWCAP>(lds4, in, a, blk, 0, min(CC, R), t0);
-  __syncthreads();
-  if (npass > 1) stage_f32_async<NWAVE, ROWCAP>(lds4 + BUF, in, a, blk, CC, min(CC, R - CC), t0);
-  win_pload<TP, DPW, NWIN>(ba, bb, row_addr(0, e0[0]), e0[1]);
-
-  // Row c is summed from bank c & 1 (its table offsets include that bank's
-  // base) while row c + 1's window loads into the other.
-  for (int c = 0; c < R; ++c) {
-    const int cn = c + 1 < R ? c + 1 : c;
-    if (c + 1 < R && (c + 1) % CC == 0) {
-      const int pn = (c + 1) / CC;
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      fix_tail_async<NWAVE, ROWCAP>(lds4 + (pn & 1) * BUF, in, a, blk, pn * CC, min(CC, R - pn * CC), t0);
-      __syncthreads();
-      if (pn + 1 < npass)
-        stage_f32_async<NWAVE, ROWCAP>(lds4 + ((pn + 1) & 1) * BUF, in, a, blk, (pn + 1) * CC,
-                                       min(CC, R - (pn + 1) * CC), t0);
-    }
-    const int c2 = min(c + 2, R - 1);
-    E e2;
-    float w2 = 0.f;
-    win_pstep<TP, DPW, NWIN, WEIGHTED>(acc, ba, bb, row_addr(cn, e1[0]), e1[1], (c + 1) & 1, e0,
-                                       wav + (size_t)c2 * WI, e2, w0, WEIGHTED ? w_in + c2 : nullptr, w2);
-    e0 = e1;
-    e1 = e2;
-    w0 = w1;
-    w1 = w2;
-  }
-  win_store<TP, DPW, NWAVE, ADJ>(a, acc, tt, rt, beam);
-}
-
-template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool PIPE, bool WEIGHTED, bool ADJ>
-__device__ __forceinline__ void win_any(const TileArgs& a, int tt, int rt, int beam, float4* lds4) {
-  if constexpr (PIPE)
-    win_tile_pipe<TP, DPW, NWAVE, NWIN, CC, ROWCAP, WEIGHTED, ADJ>(a, tt, rt, beam, lds4);
-  else
-    win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, WEIGHTED, ADJ>(a, tt, rt, beam, lds4);
-}
-
-template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool PIPE, bool WEIGHTED, bool ADJ>
+template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool WEIGHTED, bool ADJ>
 __global__ __launch_bounds__(64 * NWAVE) void win_kernel(TileArgs a) {
   __shared__ float4 lds4[NBUF * CC * ROWCAP / 4];
   const int nblk = a.n_time_tiles * a.n_row_tiles;
   const int W = xcd_remap(blockIdx.x, nblk);
-  win_any<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, PIPE, WEIGHTED, ADJ>(a, W / a.n_row_tiles, W % a.n_row_tiles,
-                                                                       blockIdx.y, lds4);
+  win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, WEIGHTED, ADJ>(a, W / a.n_row_tiles, W % a.n_row_tiles,
+                                                                   blockIdx.y, lds4);
 }
 
 // Persistent form for batches of beams.  The work table is split into one
@@ -409,7 +339,7 @@ __global__ __launch_bounds__(64 * NWAVE) void win_kernel(TileArgs a) {
 // Every beam shares the variant; per-beam pointers and tables come from its
 // descriptor.  The counters (one per queue, 128 bytes apart) are cleared by a
 // separate kernel before each launch.
-template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool PIPE, bool WEIGHTED>
+template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool WEIGHTED>
 __global__ __launch_bounds__(64 * NWAVE) void win_persistent(const BeamDesc* __restrict__ beams,
                                                              const int32_t* __restrict__ order,
                                                              const int32_t* __restrict__ qoff, int* counters) {
@@ -429,7 +359,7 @@ __global__ __launch_bounds__(64 * NWAVE) void win_persistent(const BeamDesc* __r
       const int local = order[2 * (q0 + k) + 1];
       const TileArgs& a = beams[b].a;
       const int tt = local / a.n_row_tiles, rt = local % a.n_row_tiles;
-      win_any<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, PIPE, WEIGHTED, false>(a, tt, rt, 0, lds4);
+      win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, WEIGHTED, false>(a, tt, rt, 0, lds4);
     }
   }
 }
@@ -678,22 +608,26 @@ __global__ __launch_bounds__(64 * NWAVE) void u8_kernel(TileArgs a) {
 // uint8 -> int32 tile engine on byte-shifted rows.  Each input row is staged
 // as four copies shifted by 0..3 bytes (stage_u8_shift4), so the four samples
 // a lane needs at any delay are one aligned LDS dword: one 4-byte LDS read
-// per 4 adds.  The bytes are split into two packed 16-bit pairs with byte
-// permutes (samples {0, 2} and {1, 3}) and two input rows are summed per
-// three-operand add, 0.75 vector operations per add.  A 16-bit lane holds
-// the sum of at most 257 bytes; WIDE variants move the packed sums into
-// int32 accumulators every 256 input rows, the others accept at most 257
-// input rows.  Sums are exact integers, so the order does not matter.
+// per 4 adds.  The table gives, per (wave tile, input row), each output row's
+// dword offset into the staged copies, so a read costs one address add.
+// For a dword v = (b0, b1, b2, b3) the lane keeps two sums over rows:
+//   E += v & 0x00FF00FF     (16-bit lanes: sum b0, sum b2)
+//   U += v >> 8             (sum b1 + 2^8 sum b2 + 2^16 sum b3)
+// four two-operand integer operations, which issue at the full rate, per 4
+// adds.  Over at most 256 rows neither overflows, and
+//   sum b0 = E & 0xFFFF, sum b2 = E >> 16, U - 2^8 sum b2 = sum b1 + 2^16 sum b3.
+// WIDE variants move these into int32 sums every 256 input rows; the others
+// accept at most 256 input rows.  Sums are exact integers, so the order does
+// not matter.
 // ---------------------------------------------------------------------------
 template <int Q, int DPW, int NWAVE, int CC, int ROWCAP, bool WIDE>
 __global__ __launch_bounds__(64 * NWAVE) void u8s_kernel(TileArgs a) {
   constexpr int ST = 256 * Q;
   constexpr int DT = NWAVE * DPW;
-  constexpr int RW = ROWCAP / 4;  // dwords per copy of a row
-  static_assert(DPW <= 8 && CC % 2 == 0 && 256 % CC == 0, "unsupported shape");
-  typedef ent4_t E;
-  constexpr uint32_t SEL_EVEN = 0x0C020C00u;  // bytes {0, 2} into 16-bit lanes
-  constexpr uint32_t SEL_ODD = 0x0C030C01u;   // bytes {1, 3}
+  constexpr int WI = DPW <= 4 ? 4 : 8;  // ints per table entry
+  static_assert(DPW == 2 || DPW == 4 || DPW == 8, "unsupported rows per wave");
+  static_assert(256 % CC == 0, "a flush every 256 rows must fall on a pass boundary");
+  typedef typename std::conditional<(WI == 4), ent4_t, ent8_t>::type E;
   __shared__ uint4 lds[4 * CC * ROWCAP / 16];
   __shared__ E tab[NWAVE][CC];
   const int nblk = a.n_time_tiles * a.n_row_tiles;
@@ -705,27 +639,31 @@ __global__ __launch_bounds__(64 * NWAVE) void u8s_kernel(TileArgs a) {
   const int t0 = tt * ST;
   const uint8_t* in = static_cast<const uint8_t*>(a.in) + (int64_t)beam * a.in_beam_stride;
   const int32_t* blk = uniform_ptr(a.blk + (size_t)rt * a.rows_in * 2);
-  const int32_t* __restrict__ wav = uniform_ptr(a.wav + (size_t)wt * a.rows_in * 4);
+  const int32_t* __restrict__ wav = uniform_ptr(a.wav + (size_t)wt * a.rows_in * WI);
   const uint32_t* lds32 = reinterpret_cast<const uint32_t*>(lds) + lane;
   int32_t* out = static_cast<int32_t*>(a.out) + (int64_t)beam * a.out_beam_stride;
   const int npass = (a.rows_in + CC - 1) / CC;
 
-  uint32_t ev[DPW][Q], od[DPW][Q];
+  uint32_t ev[DPW][Q], hi[DPW][Q];
   int acc[WIDE ? DPW : 1][WIDE ? Q : 1][4];
 #pragma unroll
   for (int j = 0; j < DPW; ++j)
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      ev[j][q] = od[j][q] = 0u;
+      ev[j][q] = hi[j][q] = 0u;
       if (WIDE)
 #pragma unroll
         for (int k = 0; k < 4; ++k) acc[WIDE ? j : 0][WIDE ? q : 0][k] = 0;
     }
 
-  // dword offset of the lane-0 read of output row jj in staged row cl
-  auto base_of = [&](const uint32_t* cw, int jj, int cl) -> int {
-    const uint32_t o = (cw[jj >> 1] >> (16 * (jj & 1))) & 0xFFFFu;
-    return (int)(((o & 3u) * CC + cl) * RW + (o >> 2));
+  // the four sample sums of (output row j, dword q) from the packed sums
+  auto unpack = [&](int j, int q, int* s4) {
+    const uint32_t s2 = ev[j][q] >> 16;
+    const uint32_t u = hi[j][q] - (s2 << 8);
+    s4[0] = (int)(ev[j][q] & 0xFFFFu);
+    s4[1] = (int)(u & 0xFFFFu);
+    s4[2] = (int)s2;
+    s4[3] = (int)(u >> 16);
   };
 
   for (int p = 0; p < npass; ++p) {
@@ -733,42 +671,18 @@ __global__ __launch_bounds__(64 * NWAVE) void u8s_kernel(TileArgs a) {
     const int ncc = min(CC, a.rows_in - c0);
     __syncthreads();
     stage_u8_shift4<NWAVE, CC, ROWCAP>(lds, in, a, blk, c0, ncc, t0);
-    if (lane < ncc) tab[wave][lane] = *reinterpret_cast<const E*>(wav + (size_t)(c0 + lane) * 4);
+    if (lane < ncc) tab[wave][lane] = *reinterpret_cast<const E*>(wav + (size_t)(c0 + lane) * WI);
     __syncthreads();
-    int cl = 0;
-    for (; cl + 1 < ncc; cl += 2) {
-      const E e0 = tab[wave][cl], e1 = tab[wave][cl + 1];
-      uint32_t c0w[4], c1w[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        c0w[q] = (uint32_t)__builtin_amdgcn_readfirstlane(e0[q]);
-        c1w[q] = (uint32_t)__builtin_amdgcn_readfirstlane(e1[q]);
-      }
+    for (int cl = 0; cl < ncc; ++cl) {
+      const E e = tab[wave][cl];
 #pragma unroll
       for (int jj = 0; jj < DPW; ++jj) {
-        const uint32_t* p0 = lds32 + base_of(c0w, jj, cl);
-        const uint32_t* p1 = lds32 + base_of(c1w, jj, cl + 1);
+        const uint32_t* pr = lds32 + __builtin_amdgcn_readfirstlane(e[jj]);
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-          const uint32_t v0 = p0[64 * q], v1 = p1[64 * q];
-          ev[jj][q] += __builtin_amdgcn_perm(0u, v0, SEL_EVEN) + __builtin_amdgcn_perm(0u, v1, SEL_EVEN);
-          od[jj][q] += __builtin_amdgcn_perm(0u, v0, SEL_ODD) + __builtin_amdgcn_perm(0u, v1, SEL_ODD);
-        }
-      }
-    }
-    if (cl < ncc) {
-      const E e0 = tab[wave][cl];
-      uint32_t c0w[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) c0w[q] = (uint32_t)__builtin_amdgcn_readfirstlane(e0[q]);
-#pragma unroll
-      for (int jj = 0; jj < DPW; ++jj) {
-        const uint32_t* p0 = lds32 + base_of(c0w, jj, cl);
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          const uint32_t v0 = p0[64 * q];
-          ev[jj][q] += __builtin_amdgcn_perm(0u, v0, SEL_EVEN);
-          od[jj][q] += __builtin_amdgcn_perm(0u, v0, SEL_ODD);
+          const uint32_t v = pr[64 * q];
+          ev[jj][q] += v & 0x00FF00FFu;
+          hi[jj][q] += v >> 8;
         }
       }
     }
@@ -777,12 +691,11 @@ __global__ __launch_bounds__(64 * NWAVE) void u8s_kernel(TileArgs a) {
       for (int j = 0; j < DPW; ++j)
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-          int* A = acc[WIDE ? j : 0][WIDE ? q : 0];
-          A[0] += (int)(ev[j][q] & 0xFFFFu);
-          A[1] += (int)(od[j][q] & 0xFFFFu);
-          A[2] += (int)(ev[j][q] >> 16);
-          A[3] += (int)(od[j][q] >> 16);
-          ev[j][q] = od[j][q] = 0u;
+          int s4[4];
+          unpack(j, q, s4);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) acc[WIDE ? j : 0][WIDE ? q : 0][k] += s4[k];
+          ev[j][q] = hi[j][q] = 0u;
         }
     }
   }
@@ -794,26 +707,23 @@ __global__ __launch_bounds__(64 * NWAVE) void u8s_kernel(TileArgs a) {
       int32_t* orow = out + (int64_t)r * a.out_stride;
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        int s[4];
+        int s4[4];
         if (WIDE) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) s[e] = acc[WIDE ? jj : 0][WIDE ? q : 0][e];
+          for (int e = 0; e < 4; ++e) s4[e] = acc[WIDE ? jj : 0][WIDE ? q : 0][e];
         } else {
-          s[0] = (int)(ev[jj][q] & 0xFFFFu);
-          s[1] = (int)(od[jj][q] & 0xFFFFu);
-          s[2] = (int)(ev[jj][q] >> 16);
-          s[3] = (int)(od[jj][q] >> 16);
+          unpack(jj, q, s4);
         }
         const int t = t0 + 4 * lane + 256 * q;
         if (t + 4 <= a.nout) {
-          __builtin_nontemporal_store(s[0], orow + t + 0);
-          __builtin_nontemporal_store(s[1], orow + t + 1);
-          __builtin_nontemporal_store(s[2], orow + t + 2);
-          __builtin_nontemporal_store(s[3], orow + t + 3);
+          __builtin_nontemporal_store(s4[0], orow + t + 0);
+          __builtin_nontemporal_store(s4[1], orow + t + 1);
+          __builtin_nontemporal_store(s4[2], orow + t + 2);
+          __builtin_nontemporal_store(s4[3], orow + t + 3);
         } else {
 #pragma unroll
           for (int e = 0; e < 4; ++e)
-            if (t + e < a.nout) orow[t + e] = s[e];
+            if (t + e < a.nout) orow[t + e] = s4[e];
         }
       }
     }
@@ -911,30 +821,27 @@ __global__ __launch_bounds__(256) void reduce_gradw_kernel(const double* __restr
 // Variant tables and launchers.
 // ---------------------------------------------------------------------------
 // (index, TP samples per lane, DPW rows per wave, NWAVE, NWIN window registers,
-//  CC rows per LDS pass, ROWCAP floats per LDS row, NBUF LDS buffers, PIPE:
-//  two register windows with the next row's loads in flight)
-// A lane owns TP consecutive samples; TP/4 odd (12, 20) keeps its 16-byte LDS
-// reads free of bank conflicts.
-#define F32_VARIANTS(X)                                             \
-  X(0, 12, 4, 4, 36, 8, 1024, 1, 0)   /* 16 DMs x 768             */ \
-  X(1, 12, 4, 4, 48, 8, 1024, 1, 0)   /* 16 DMs x 768, wide spans */ \
-  X(2, 8, 8, 4, 64, 8, 1024, 1, 0)    /* 32 DMs x 512             */ \
-  X(3, 16, 8, 4, 72, 8, 2048, 1, 0)   /* 32 DMs x 1024            */ \
-  X(4, 8, 4, 4, 48, 16, 1024, 1, 0)   /* 16 DMs x 512             */ \
-  X(5, 16, 4, 4, 64, 8, 2048, 1, 0)   /* 16 DMs x 1024            */ \
-  X(6, 12, 4, 4, 36, 4, 1024, 2, 0)   /* 16 DMs x 768, async      */ \
-  X(7, 12, 8, 4, 56, 4, 1024, 2, 0)   /* 32 DMs x 768, async      */ \
-  X(8, 20, 4, 4, 44, 4, 1536, 2, 0)   /* 16 DMs x 1280, async     */ \
-  X(9, 12, 4, 8, 36, 4, 1024, 2, 0)   /* 32 DMs x 768, async      */ \
-  X(10, 12, 8, 8, 56, 4, 1280, 2, 0)  /* 64 DMs x 768, async      */ \
-  X(11, 12, 4, 4, 48, 4, 1024, 2, 0)  /* 16 DMs x 768, async      */ \
-  X(12, 8, 8, 4, 64, 4, 1024, 2, 0)   /* 32 DMs x 512, async      */ \
-  X(13, 20, 4, 4, 44, 4, 1536, 2, 1)  /* 16 DMs x 1280, pipelined */ \
-  X(14, 20, 4, 8, 44, 8, 1536, 2, 1)  /* 32 DMs x 1280, pipelined */ \
-  X(15, 12, 4, 4, 36, 4, 1024, 2, 1)  /* 16 DMs x 768, pipelined  */ \
-  X(16, 12, 4, 6, 36, 6, 1024, 2, 1)  /* 24 DMs x 768, pipelined  */ \
-  X(17, 12, 8, 4, 56, 4, 1024, 2, 1)  /* 32 DMs x 768, pipelined  */ \
-  X(18, 12, 8, 8, 56, 8, 1280, 2, 1)  /* 64 DMs x 768, pipelined  */
+//  CC rows per LDS pass, ROWCAP floats per LDS row, NBUF LDS buffers)
+// A lane owns TP consecutive samples; TP/4 odd (12, 20, 28) keeps its 16-byte
+// LDS reads free of bank conflicts.
+#define F32_VARIANTS(X)                                          \
+  X(0, 12, 4, 4, 36, 8, 1024, 1)   /* 16 DMs x 768             */ \
+  X(1, 12, 4, 4, 48, 8, 1024, 1)   /* 16 DMs x 768, wide spans */ \
+  X(2, 8, 8, 4, 64, 8, 1024, 1)    /* 32 DMs x 512             */ \
+  X(3, 16, 8, 4, 72, 8, 2048, 1)   /* 32 DMs x 1024            */ \
+  X(4, 8, 4, 4, 48, 16, 1024, 1)   /* 16 DMs x 512             */ \
+  X(5, 16, 4, 4, 64, 8, 2048, 1)   /* 16 DMs x 1024            */ \
+  X(6, 12, 4, 4, 36, 4, 1024, 2)   /* 16 DMs x 768, async      */ \
+  X(7, 12, 8, 4, 56, 4, 1024, 2)   /* 32 DMs x 768, async      */ \
+  X(8, 20, 4, 4, 44, 4, 1536, 2)   /* 16 DMs x 1280, async     */ \
+  X(9, 12, 4, 8, 36, 4, 1024, 2)   /* 32 DMs x 768, async      */ \
+  X(10, 12, 8, 8, 56, 4, 1280, 2)  /* 64 DMs x 768, async      */ \
+  X(11, 12, 4, 4, 48, 4, 1024, 2)  /* 16 DMs x 768, async      */ \
+  X(12, 8, 8, 4, 64, 4, 1024, 2)   /* 32 DMs x 512, async      */ \
+  X(13, 20, 8, 4, 56, 4, 1536, 2)  /* 32 DMs x 1280, async     */ \
+  X(14, 28, 4, 4, 48, 4, 2048, 2)  /* 16 DMs x 1792, async     */ \
+  X(15, 20, 8, 8, 56, 4, 1792, 2)  /* 64 DMs x 1280, async     */ \
+  X(16, 28, 4, 8, 48, 4, 2048, 2)  /* 32 DMs x 1792, async     */
 
 // (index, Q dwords per lane, DPW, NWAVE, CC rows per LDS pass, ROWCAP bytes)
 #define U8_VARIANTS(X)                                      \
@@ -953,22 +860,21 @@ __global__ __launch_bounds__(256) void reduce_gradw_kernel(const double* __restr
 
 // Byte-shifted variants: (index, Q, DPW, NWAVE, CC, ROWCAP bytes per copy, WIDE)
 #define U8S_VARIANTS(X)                                      \
-  X(12, 4, 4, 4, 8, 1792, false) /* 16 DMs x 1024      */   \
-  X(13, 2, 4, 4, 8, 1280, false) /* 16 DMs x 512       */   \
-  X(14, 4, 4, 4, 4, 1792, false) /* 16 DMs x 1024      */   \
-  X(15, 2, 8, 4, 8, 1792, false) /* 32 DMs x 512       */   \
-  X(16, 4, 2, 4, 8, 1536, false) /*  8 DMs x 1024      */   \
-  X(17, 2, 4, 8, 4, 1792, false) /* 32 DMs x 512       */   \
-  X(18, 4, 4, 4, 8, 1792, true)  /* 16 DMs x 1024, wide */  \
-  X(19, 2, 4, 4, 8, 1280, true)  /* 16 DMs x 512, wide  */
+  X(12, 4, 4, 4, 4, 1792, false) /* 16 DMs x 1024      */   \
+  X(13, 2, 4, 8, 4, 1792, false) /* 32 DMs x 512       */   \
+  X(14, 4, 2, 4, 4, 1536, false) /*  8 DMs x 1024      */   \
+  X(15, 4, 8, 4, 4, 2304, false) /* 32 DMs x 1024      */   \
+  X(16, 2, 4, 4, 4, 1280, false) /* 16 DMs x 512       */   \
+  X(17, 4, 4, 4, 2, 1792, false) /* 16 DMs x 1024      */   \
+  X(18, 4, 4, 4, 4, 1792, true)  /* 16 DMs x 1024, wide */  \
+  X(19, 2, 4, 8, 4, 1792, true)  /* 32 DMs x 512, wide  */
 
 const std::vector<Variant>& variants_f32() {
   static const std::vector<Variant> v = [] {
     std::vector<Variant> r;
-#define MAKE_F32(ID, TP, DPW, NW, NWIN, CC, RC, NB, PIPE)                                                  \
-  r.push_back(Variant{PIPE ? "win_tp" #TP "_dpw" #DPW "_nw" #NW "_win" #NWIN "_cc" #CC "_pipe"               \
-                           : "win_tp" #TP "_dpw" #DPW "_nw" #NW "_win" #NWIN "_cc" #CC "_buf" #NB,            \
-                      KIND_WIN_F32, TP, DPW, NW, NWIN, CC, RC, NB, ID, PIPE});
+#define MAKE_F32(ID, TP, DPW, NW, NWIN, CC, RC, NB)                                                         \
+  r.push_back(Variant{"win_tp" #TP "_dpw" #DPW "_nw" #NW "_win" #NWIN "_cc" #CC "_buf" #NB, KIND_WIN_F32, TP,   \
+                      DPW, NW, NWIN, CC, RC, NB, ID});
     F32_VARIANTS(MAKE_F32)
 #undef MAKE_F32
     return r;
@@ -1005,16 +911,15 @@ hipError_t launch_tiled(const Variant& v, const TileArgs& a, int nbeam, bool adj
   const dim3 block(64 * v.nwave);
   const bool weighted = adjoint ? false : (a.w_in != nullptr);
   if (v.kind == KIND_WIN_F32) {
-#define LAUNCH_F32(ID, TP, DPW, NW, NWIN, CC, RC, NB, PIPE)                                                     \
-  if (v.id == ID) {                                                                                             \
-    if (adjoint)                                                                                                \
-      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, PIPE, false, true>), grid, block, 0, s, a); \
-    else if (weighted)                                                                                          \
-      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, PIPE, true, false>), grid, block, 0, s, a); \
-    else                                                                                                        \
-      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, PIPE, false, false>), grid, block, 0, s,    \
-                         a);                                                                                    \
-    return hipGetLastError();                                                                                   \
+#define LAUNCH_F32(ID, TP, DPW, NW, NWIN, CC, RC, NB)                                                     \
+  if (v.id == ID) {                                                                                       \
+    if (adjoint)                                                                                          \
+      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, false, true>), grid, block, 0, s, a); \
+    else if (weighted)                                                                                    \
+      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, true, false>), grid, block, 0, s, a); \
+    else                                                                                                  \
+      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, false, false>), grid, block, 0, s, a); \
+    return hipGetLastError();                                                                             \
   }
     F32_VARIANTS(LAUNCH_F32)
 #undef LAUNCH_F32
@@ -1040,15 +945,15 @@ hipError_t launch_tiled(const Variant& v, const TileArgs& a, int nbeam, bool adj
 hipError_t launch_batched(const Variant& v, const BeamDesc* d_beams, bool weighted, const int32_t* d_order,
                           const int32_t* d_qoff, int* d_counter, int grid, hipStream_t s) {
   const dim3 block(64 * v.nwave);
-#define LAUNCH_P(ID, TP, DPW, NW, NWIN, CC, RC, NB, PIPE)                                                        \
-  if (v.id == ID) {                                                                                              \
-    if (weighted)                                                                                                \
-      hipLaunchKernelGGL((win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, PIPE, true>), dim3(grid), block, 0, s,  \
-                         d_beams, d_order, d_qoff, d_counter);                                                   \
-    else                                                                                                         \
-      hipLaunchKernelGGL((win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, PIPE, false>), dim3(grid), block, 0, s, \
-                         d_beams, d_order, d_qoff, d_counter);                                                   \
-    return hipGetLastError();                                                                                    \
+#define LAUNCH_P(ID, TP, DPW, NW, NWIN, CC, RC, NB)                                                        \
+  if (v.id == ID) {                                                                                        \
+    if (weighted)                                                                                          \
+      hipLaunchKernelGGL((win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, true>), dim3(grid), block, 0, s,  \
+                         d_beams, d_order, d_qoff, d_counter);                                             \
+    else                                                                                                   \
+      hipLaunchKernelGGL((win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, false>), dim3(grid), block, 0, s, \
+                         d_beams, d_order, d_qoff, d_counter);                                             \
+    return hipGetLastError();                                                                              \
   }
   if (v.kind == KIND_WIN_F32) {
     F32_VARIANTS(LAUNCH_P)
@@ -1059,11 +964,11 @@ hipError_t launch_batched(const Variant& v, const BeamDesc* d_beams, bool weight
 
 int batched_blocks_per_cu(const Variant& v) {
   int n = 0;
-#define OCC_P(ID, TP, DPW, NW, NWIN, CC, RC, NB, PIPE)                                                   \
-  if (v.id == ID) {                                                                                       \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(                                                     \
-            &n, win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, PIPE, false>, 64 * NW, 0) != hipSuccess)     \
-      n = 1;                                                                                              \
+#define OCC_P(ID, TP, DPW, NW, NWIN, CC, RC, NB)                                                                 \
+  if (v.id == ID) {                                                                                              \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, false>,  \
+                                                     64 * NW, 0) != hipSuccess)                                   \
+      n = 1;                                                                                                     \
     return n > 0 ? n : 1;                                                                                        \
   }
   if (v.kind == KIND_WIN_F32) {

@@ -13,13 +13,19 @@ DPW output rows (DM trials) of one wave:
      VGPRs with 16-byte reads (only as many reads as the row's delay span
      needs, ``nl``);
   2. once they have landed, issue the scalar load of the next row's table
-     entry (and weight), whose latency then hides behind the adds;
+     entry (and weight), whose latency then hides behind the adds.  The loads
+     go through buffer resources with a byte offset the step advances itself,
+     so reads past the last row return zero instead of needing a clamp;
   3. turn VGPR index mode on and, for each of the DPW rows j, set the index
      to the row's window offset o_j (one SGPR each) and add the TP window
      registers starting at o_j into the row's TP accumulators:
         acc[j][i] += win[o_j + i]        (or fma(win[o_j + i], w, acc[j][i]))
      so each accumulator receives exactly one term per input row, in input
      row order, with one rounding per term.
+
+The scalar unit is shared by the four SIMDs of a compute unit, so every
+scalar instruction in the step costs add throughput; the step keeps them to
+the index changes, the load-count tests and two waits.
 
 A lane owns TP consecutive samples, so neighbouring lanes' windows start
 4*TP bytes apart; TP/4 odd keeps the 16-byte LDS reads free of bank
@@ -42,6 +48,8 @@ VARIANTS = [
     (12, 4, 48),
     (12, 8, 56),
     (20, 4, 44),
+    (20, 8, 56),
+    (28, 4, 48),
 ]
 
 
@@ -74,9 +82,11 @@ def step(tp, dpw, nwin, weighted):
     lines.append("s_waitcnt lgkmcnt(0)")
     # the next row's table entry (and weight) load while the adds run; the
     # final wait leaves them complete when the step returns
-    lines.append(f"s_load_dwordx{ent} %[nxt], %[nptr], 0x0")
+    lines.append(f"s_buffer_load_dwordx{ent} %[nxt], %[trs], %[toff]")
+    lines.append(f"s_add_u32 %[toff], %[toff], {4 * ent}")
     if weighted:
-        lines.append("s_load_dword %[wn], %[wptr], 0x0")
+        lines.append("s_buffer_load_dword %[wn], %[wrs], %[woff]")
+        lines.append("s_add_u32 %[woff], %[woff], 4")
     for j in range(dpw):
         if j == 0:
             lines.append("s_set_gpr_idx_on %[o0], gpr_idx(SRC0)")
@@ -92,161 +102,36 @@ def step(tp, dpw, nwin, weighted):
     lines.append("s_mov_b32 m0, %[m0s]")
     lines.append("s_waitcnt lgkmcnt(0)")
     asm = "".join(f'    "{ln}\\n\\t"\n' for ln in lines)
-    outs = ['[m0s] "=&s"(m0s)', '[nxt] "=&s"(nxt)']
+    outs = ['[m0s] "=&s"(m0s)', '[nxt] "=&s"(nxt)', '[toff] "+s"(toff)']
     if weighted:
         outs.append('[wn] "=&s"(wn)')
+        outs.append('[woff] "+s"(woff)')
     for q in range(nacc // 16):
         lo = ACC0 + 16 * q
         outs.append(f'[a{q}] "+{{v[{lo}:{lo + 15}]}}"(acc[{q}])')
-    ins = ['[addr] "v"(addr)', '[nl] "s"(cur[1])', '[nptr] "s"(nptr)']
+    ins = ['[addr] "v"(addr)', '[nl] "s"(cur[1])', '[trs] "s"(trs)']
     for j in range(dpw):
         ins.append(f'[o{j}] "s"(cur[{2 + j}])')
     if weighted:
         ins.append('[w] "s"(w)')
-        ins.append('[wptr] "s"(wptr)')
+        ins.append('[wrs] "s"(wrs)')
     clob = [f'"v{w0 + r}"' for r in range(nwin)] + ['"scc"']
     wflag = "true" if weighted else "false"
     etype = f"ent{ent}_t"
     return (
         f"template <>\n"
         f"__device__ __forceinline__ void win_step<{tp}, {dpw}, {nwin}, {wflag}>(v16f* acc, uint32_t addr,\n"
-        f"    const {etype}& cur, const int32_t* nptr, {etype}& nxt, float w, const float* wptr, float& wn) {{\n"
+        f"    const {etype}& cur, {etype}& nxt, __amdgpu_buffer_rsrc_t trs, uint32_t& toff, float w,\n"
+        f"    float& wn, __amdgpu_buffer_rsrc_t wrs, uint32_t& woff) {{\n"
         f"  uint32_t m0s;\n"
         f"  (void)w;\n"
-        f"  (void)wptr;\n"
         f"  (void)wn;\n"
+        f"  (void)wrs;\n"
+        f"  (void)woff;\n"
         f"  asm volatile(\n{asm}"
         f"    : {', '.join(outs)}\n"
         f"    : {', '.join(ins)}\n"
         f"    : {', '.join(clob)});\n"
-        f"}}\n"
-    )
-
-
-# Pipelined variants (TP, DPW, NWIN window registers per bank): two register
-# windows, the next input row's loads in flight while the current row is summed.
-PIPE_VARIANTS = [
-    (20, 4, 44),
-    (12, 4, 36),
-    (12, 8, 56),
-]
-
-
-def chunks(n):
-    """Split n registers (a multiple of 4) into tuples of 16/8/4."""
-    out = []
-    for c in (16, 8, 4):
-        while n >= c:
-            out.append(c)
-            n -= c
-    return out
-
-
-def bank_struct(nwin):
-    fields = "".join(f"  v{c}f c{i};\n" for i, c in enumerate(chunks(nwin)))
-    return f"template <> struct BankT<{nwin}> {{\n{fields}}};\n"
-
-
-def bank_operands(name, base, nwin):
-    ops, r = [], base
-    for i, c in enumerate(chunks(nwin)):
-        ops.append(f'[{name}{i}] "+{{v[{r}:{r + c - 1}]}}"({name}.c{i})')
-        r += c
-    return ops
-
-
-def window_loads(w0, tp, nwin, label):
-    """nmin unconditional 16-byte reads, then one more while k < nl."""
-    lines = []
-    nmin, nmax = tp // 4 + 1, nwin // 4
-    for k in range(nmin):
-        lines.append(f"ds_read_b128 v[{w0 + 4 * k}:{w0 + 4 * k + 3}], %[addr] offset:{16 * k}")
-    for k in range(nmin, nmax):
-        lines.append(f"s_cmp_le_u32 %[nl], {k}")
-        lines.append(f"s_cbranch_scc1 {label}")
-        lines.append(f"ds_read_b128 v[{w0 + 4 * k}:{w0 + 4 * k + 3}], %[addr] offset:{16 * k}")
-    return lines
-
-
-def asm_body(lines):
-    return "".join(f'    "{ln}\\n\\t"\n' for ln in lines)
-
-
-def pipe_step(tp, dpw, nwin, weighted):
-    """Specialisation of win_pstep: load the next row's window into bank xb,
-    fetch the entry two rows ahead, and sum the current row, whose offsets
-    already include its bank (0 or nwin) and so select it through the index."""
-    nacc = tp * dpw
-    assert nacc % 16 == 0 and nwin % 4 == 0 and tp % 4 == 0
-    wa = ACC0 + nacc
-    wb = wa + nwin
-    assert wb + nwin <= 256
-    ent = entry_ints(dpw)
-    lines = ["s_mov_b32 %[m0s], m0", "s_cmp_eq_u32 %[xb], 0", "s_cbranch_scc1 .Lpload_a_%="]
-    lines += window_loads(wb, tp, nwin, ".Lpload_done_%=")
-    lines += ["s_branch .Lpload_done_%=", ".Lpload_a_%=:"]
-    lines += window_loads(wa, tp, nwin, ".Lpload_done_%=")
-    lines.append(".Lpload_done_%=:")
-    lines.append(f"s_load_dwordx{ent} %[nxt], %[nptr], 0x0")
-    if weighted:
-        lines.append("s_load_dword %[wn], %[wptr], 0x0")
-    for j in range(dpw):
-        lines.append("s_set_gpr_idx_on %[o0], gpr_idx(SRC0)" if j == 0 else f"s_set_gpr_idx_idx %[o{j}]")
-        for i in range(tp):
-            a = ACC0 + j * tp + i
-            if weighted:
-                lines.append(f"v_fma_f32 v{a}, v{wa + i}, %[w], v{a}")
-            else:
-                lines.append(f"v_add_f32 v{a}, v{wa + i}, v{a}")
-    lines.append("s_set_gpr_idx_off")
-    lines.append("s_mov_b32 m0, %[m0s]")
-    lines.append("s_waitcnt lgkmcnt(0)")
-    outs = ['[m0s] "=&s"(m0s)', '[nxt] "=&s"(nxt)']
-    if weighted:
-        outs.append('[wn] "=&s"(wn)')
-    for q in range(nacc // 16):
-        lo = ACC0 + 16 * q
-        outs.append(f'[a{q}] "+{{v[{lo}:{lo + 15}]}}"(acc[{q}])')
-    outs += bank_operands("ba", wa, nwin) + bank_operands("bb", wb, nwin)
-    ins = ['[addr] "v"(addr)', '[nl] "s"(nl)', '[xb] "s"(xb)', '[nptr] "s"(nptr)']
-    for j in range(dpw):
-        ins.append(f'[o{j}] "s"(cur[{2 + j}])')
-    if weighted:
-        ins.append('[w] "s"(w)')
-        ins.append('[wptr] "s"(wptr)')
-    wflag = "true" if weighted else "false"
-    etype = f"ent{ent}_t"
-    return (
-        f"template <>\n"
-        f"__device__ __forceinline__ void win_pstep<{tp}, {dpw}, {nwin}, {wflag}>(v16f* acc, BankT<{nwin}>& ba,\n"
-        f"    BankT<{nwin}>& bb, uint32_t addr, int nl, int xb, const {etype}& cur, const int32_t* nptr,\n"
-        f"    {etype}& nxt, float w, const float* wptr, float& wn) {{\n"
-        f"  uint32_t m0s;\n"
-        f"  (void)w;\n"
-        f"  (void)wptr;\n"
-        f"  (void)wn;\n"
-        f"  asm volatile(\n{asm_body(lines)}"
-        f"    : {', '.join(outs)}\n"
-        f"    : {', '.join(ins)}\n"
-        f"    : \"scc\");\n"
-        f"}}\n"
-    )
-
-
-def pipe_load(tp, dpw, nwin):
-    """Specialisation of win_pload: the first row's window into bank 0."""
-    wa = ACC0 + tp * dpw
-    wb = wa + nwin
-    lines = window_loads(wa, tp, nwin, ".Lpload_%=") + [".Lpload_%=:", "s_waitcnt lgkmcnt(0)"]
-    outs = bank_operands("ba", wa, nwin) + bank_operands("bb", wb, nwin)
-    return (
-        f"template <>\n"
-        f"__device__ __forceinline__ void win_pload<{tp}, {dpw}, {nwin}>(BankT<{nwin}>& ba, BankT<{nwin}>& bb,\n"
-        f"    uint32_t addr, int nl) {{\n"
-        f"  asm volatile(\n{asm_body(lines)}"
-        f"    : {', '.join(outs)}\n"
-        f"    : [addr] \"v\"(addr), [nl] \"s\"(nl)\n"
-        f"    : \"scc\");\n"
         f"}}\n"
     )
 
@@ -266,44 +151,18 @@ def main(out_path):
         "      typename std::conditional<(DPW + 2 <= 8), ent8_t, ent16_t>::type>::type type;\n",
         "  static constexpr int ints = DPW + 2 <= 4 ? 4 : DPW + 2 <= 8 ? 8 : 16;\n",
         "};\n\n",
-        "// Loads the next row's entry from nptr into nxt (and its weight from wptr into wn)\n",
-        "// while processing the current row described by cur.\n",
+        "// Sums the current row (entry cur, weight w) from its window at LDS byte\n",
+        "// address addr, and loads the next row's entry into nxt from the table\n",
+        "// resource trs at byte offset toff (and its weight into wn from wrs at\n",
+        "// woff), advancing both offsets by one row.\n",
         "template <int TP, int DPW, int NWIN, bool WEIGHTED>\n",
         "__device__ __forceinline__ void win_step(v16f* acc, uint32_t addr, const typename EntT<DPW>::type& cur,\n",
-        "    const int32_t* nptr, typename EntT<DPW>::type& nxt, float w, const float* wptr, float& wn);\n\n",
+        "    typename EntT<DPW>::type& nxt, __amdgpu_buffer_rsrc_t trs, uint32_t& toff, float w, float& wn,\n",
+        "    __amdgpu_buffer_rsrc_t wrs, uint32_t& woff);\n\n",
     ]
     for tp, dpw, nwin in VARIANTS:
         for weighted in (False, True):
             parts.append(step(tp, dpw, nwin, weighted))
-            parts.append("\n")
-    parts += [
-        "typedef float v4f __attribute__((ext_vector_type(4)));\n",
-        "typedef float v8f __attribute__((ext_vector_type(8)));\n",
-        "typedef float v32f __attribute__((ext_vector_type(32)));\n",
-        "// One register window: NWIN VGPRs at a fixed place, as a few register tuples.\n",
-        "template <int NWIN> struct BankT;\n",
-    ]
-    for nwin in sorted({v[2] for v in PIPE_VARIANTS}):
-        parts.append(bank_struct(nwin))
-    parts += [
-        "\n// Pipelined step: loads the window of the next row (LDS address addr, nl\n",
-        "// 16-byte reads) into bank xb (0 or 1) while summing the current row (entry\n",
-        "// cur, whose offsets include its bank's base, and weight w), and fetches the\n",
-        "// entry (and weight) two rows ahead from nptr (wptr) into nxt (wn).\n",
-        "// Everything has landed on return.\n",
-        "template <int TP, int DPW, int NWIN, bool WEIGHTED>\n",
-        "__device__ __forceinline__ void win_pstep(v16f* acc, BankT<NWIN>& ba, BankT<NWIN>& bb, uint32_t addr, int nl,\n",
-        "    int xb, const typename EntT<DPW>::type& cur, const int32_t* nptr, typename EntT<DPW>::type& nxt,\n",
-        "    float w, const float* wptr, float& wn);\n",
-        "// Loads the first row's window into bank 0 and waits for it.\n",
-        "template <int TP, int DPW, int NWIN>\n",
-        "__device__ __forceinline__ void win_pload(BankT<NWIN>& ba, BankT<NWIN>& bb, uint32_t addr, int nl);\n\n",
-    ]
-    for tp, dpw, nwin in PIPE_VARIANTS:
-        parts.append(pipe_load(tp, dpw, nwin))
-        parts.append("\n")
-        for weighted in (False, True):
-            parts.append(pipe_step(tp, dpw, nwin, weighted))
             parts.append("\n")
     text = "".join(parts)
     if os.path.exists(out_path) and open(out_path).read() == text:

@@ -40,13 +40,17 @@ struct Variant {
   int rowcap;  // LDS row capacity (f32: elements, u8: bytes)
   int nbuf;    // LDS buffers: 1 = synchronous staging, 2 = asynchronous double buffering
   int id;      // index in the variant list
-  // f32: 0 = one register window, 1 = two (pipelined); u8: 0 = one LDS copy per row, int32 sums;
-  // 1 = four byte-shifted copies, packed 16-bit sums (at most 257 input rows); 2 = as 1, flushed to int32
+  // u8 only: 0 = one LDS copy per row, int32 sums; 1 = four byte-shifted copies, packed sums (at most
+  // 256 input rows); 2 = as 1, flushed to int32 sums every 256 rows
   int mode = 0;
   int st() const { return kind == KIND_WIN_F32 ? 64 * tp : 256 * tp; }
   int dt() const { return nwave * dpw; }
-  // ints per wave-table entry: f32 {win_start, nl, one offset per row} padded to 4/8/16; u8 packed u16 offsets
-  int wav_ints() const { return kind == KIND_WIN_F32 ? (dpw + 2 <= 4 ? 4 : dpw + 2 <= 8 ? 8 : 16) : 4; }
+  // ints per wave-table entry: f32 {win_start, nl, one offset per row} padded to 4/8/16; u8 packed u16
+  // offsets (mode 0) or one LDS dword offset per row (byte-shifted modes)
+  int wav_ints() const {
+    if (kind == KIND_WIN_F32) return dpw + 2 <= 4 ? 4 : dpw + 2 <= 8 ? 8 : 16;
+    return mode == 0 ? 4 : (dpw <= 4 ? 4 : 8);
+  }
 };
 
 const std::vector<Variant>& variants_f32();
@@ -55,7 +59,7 @@ const std::vector<Variant>& variants_u8();
 // Host-built tile tables for one variant on one delay matrix.
 //   blk[row_tile][rows_in]            {stage_base, stage_len}
 //   wav[wave_tile][rows_in][wav_ints] f32: {win_start, nl, offset of each row...}
-//                                      u8:  {packed u16 offsets...}
+//                                      u8:  {packed u16 offsets...} or {LDS dword offset of each row...}
 struct Tables {
   int variant = -1;
   int n_row_tiles = 0;

@@ -67,8 +67,8 @@ typedef std::function<int(int, int)> DelayFn;
 static bool build_tables(const Variant& v, int rows_out, int rows_in, const DelayFn& delay, std::vector<int32_t>& blk,
                          std::vector<int32_t>& wav, int& n_row_tiles, int& max_stage, std::string& why) {
   const int DT = v.dt(), DPW = v.dpw, NW = v.nwave, WI = v.wav_ints();
-  if (v.kind == KIND_TILE_U8 && v.mode == 1 && rows_in > 257) {
-    why = "more than 257 input rows overflow its 16-bit packed sums";
+  if (v.kind == KIND_TILE_U8 && v.mode == 1 && rows_in > 256) {
+    why = "more than 256 input rows overflow its packed sums";
     return false;
   }
   n_row_tiles = (rows_out + DT - 1) / DT;
@@ -97,8 +97,7 @@ static bool build_tables(const Variant& v, int rows_out, int rows_in, const Dela
               return false;
             }
             maxo = std::max(maxo, o);
-            // pipelined variants sum row c from register bank c & 1
-            e[2 + j] = o + ((v.mode == 1 && (c & 1)) ? v.nwin : 0);
+            e[2 + j] = o;
           }
           const int nl = std::max(v.tp / 4 + 1, (v.tp + maxo + 3) / 4);
           e[0] = ws;
@@ -126,7 +125,12 @@ static bool build_tables(const Variant& v, int rows_out, int rows_in, const Dela
               why = "delay span exceeds the 16-bit offset range";
               return false;
             }
-            e[j / 2] |= (int32_t)((uint32_t)o << (16 * (j % 2)));
+            if (v.mode == 0) {
+              e[j / 2] |= (int32_t)((uint32_t)o << (16 * (j % 2)));
+            } else {
+              // dword index into the staged copies: copy o & 3, row slot c % cc
+              e[j] = ((o & 3) * v.cc + c % v.cc) * (v.rowcap / 4) + (o >> 2);
+            }
             need = std::max(need, (o & ~3) + 256 * v.tp + 4);
           }
         }

@@ -18,6 +18,8 @@ Prints one JSON object per experiment:
 * ``realtime_beams`` (Section 5.1): Apertif-like beams with 2,000 DMs
   dedispersed per second of compute, i.e. beams one GPU keeps up with in real
   time (the paper: 9 per HD7970).
+* ``streaming``: the same as a stream of consecutive 1 s chunks with a
+  max-delay halo, each chunk one graph replay, checked against one long run.
 
 All inputs are synthetic (seeded noise); only timings are reported.
 """
@@ -116,6 +118,43 @@ def realtime_beams(nbeams=64, nd=2000):
             "paper_hd7970_beams": 9}
 
 
+def streaming(nbeams=16, nchunks=4, nd=2000):
+    """Consecutive 1 s chunks of Apertif-like beams with a max-delay halo
+    (Section 5.1's real-time set-up, Section 2's input length): each beam's
+    samples sit in one long row per channel; chunk k reads samples
+    [k*S, (k+1)*S + max_delay) in place, so consecutive chunks overlap by the
+    halo and nothing is copied.  One graph-captured batch per chunk offset is
+    replayed in order.  Checks that the chunked outputs equal one long run,
+    then reports the beams kept in real time."""
+    f, ts, ns, step, dtype = _setup("apertif")
+    plans, xs, outs = [], [], []
+    for b in range(nbeams):
+        p = Plan(f, ts, np.arange(nd) * step)
+        plans.append(p)
+        xs.append(_input(len(f), nchunks * ns + p.max_delay, dtype, 300 + b))
+        outs.append(empty_rows(1, nd, nchunks * ns, torch.float32, "cuda"))
+    batches = []
+    for k in range(nchunks):
+        xin = [x[:, :, k * ns: (k + 1) * ns + p.max_delay] for x, p in zip(xs, plans)]
+        oin = [o[:, :, k * ns: (k + 1) * ns] for o in outs]
+        batches.append(Batch(plans, xin, oin, tune=(k == 0)))
+        if k > 0:
+            batches[k].set_variant(batches[0].variant)
+
+    def run():
+        for bt in batches:
+            bt.execute()
+    ms = _time(run, reps=3)
+    # the chunked result equals one long run of each beam
+    ok = True
+    for x, p, o in zip(xs[:2], plans[:2], outs[:2]):
+        whole = dedisperse(x, p, nsamp=nchunks * ns)
+        ok = ok and bool(torch.equal(whole, o))
+    seconds_of_data = nbeams * nchunks * ns * ts
+    return {"beams": nbeams, "chunks": nchunks, "chunk_s": ns * ts, "ndm": nd, "halo_samples": plans[0].max_delay,
+            "ms": ms, "chunked_equals_whole": ok, "beams_realtime": seconds_of_data / (ms * 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true")
@@ -129,6 +168,7 @@ def main():
                           "rows": tuned_vs_generic(name, [ndms[-1]], perfect=True)}), flush=True)
     print(json.dumps({"experiment": "histogram", "setup": "apertif", "ndm": 2048, "ms": histogram()}), flush=True)
     print(json.dumps({"experiment": "realtime_beams", **realtime_beams(16 if args.quick else 64)}), flush=True)
+    print(json.dumps({"experiment": "streaming", **streaming(8 if args.quick else 16)}), flush=True)
     print(f"experiments done in {time.time() - t0:.1f} s", file=sys.stderr)
 
 

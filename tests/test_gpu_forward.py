@@ -197,11 +197,12 @@ def test_u8_ragged():
             assert np.array_equal(out.cpu().numpy(), ref), (nc, nd, ns, v)
 
 
-@pytest.mark.parametrize("nc", [257, 258, 600])
+@pytest.mark.parametrize("nc", [256, 257, 600])
 def test_u8_many_rows_packed_sums(nc):
-    """Sums past 16 bits: 257 rows of 255 is the largest sum a packed 16-bit
-    lane holds (65535); 258 and 600 rows need the int32 flush of the wide
-    byte-shifted variants (the narrow ones must refuse such plans)."""
+    """Sums past 16 bits: 256 rows of 255 are the most the packed sums of the
+    byte-shifted variants hold (the shifted-dword sum stays below 2^32); 257
+    and 600 rows need the int32 flush of the wide variants (the narrow ones
+    must refuse such plans)."""
     dd = _dd()
     rng = np.random.default_rng(nc)
     f = 1270.0 + (np.arange(nc) + 0.5) * 300.0 / nc
@@ -218,7 +219,7 @@ def test_u8_many_rows_packed_sums(nc):
     narrow = [i for i, n in enumerate(names) if n.startswith("u8s_") and not n.endswith("_wide")]
     wide = [i for i, n in enumerate(names) if n.endswith("_wide")]
     assert wide and all(v in vs for v in wide)
-    if nc > 257:
+    if nc > 256:
         assert not any(v in vs for v in narrow)
     else:
         assert all(v in vs for v in narrow)
