@@ -113,17 +113,21 @@ def cpu_baseline(beam, target_s):
     dtc = time.perf_counter() - t
     nd = int(ncal * target_s / max(dtc, 1e-6))
     nd = max(nth, nd - nd % nth)
+    reps = 1
     if nd > beam.ndm:  # the whole beam is cheaper than the target: repeat it
+        reps = max(1, int(round(nd / beam.ndm)))
         nd = beam.ndm
     t = time.perf_counter()
-    oracle.forward_f32(x, delta[:nd], beam.nsamp)
+    for _ in range(reps):
+        oracle.forward_f32(x, delta[:nd], beam.nsamp)
     el = time.perf_counter() - t
+    what = f"first {nd} of {beam.ndm} DM trials" if nd < beam.ndm else f"all {nd} DM trials, {reps} time(s)"
     return {
-        "value": nd * beam.nsamp / el,
+        "value": reps * nd * beam.nsamp / el,
         "unit": "DM-trial·samples/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": f"one beam: {beam.nchan} channels x {beam.nsamp} samples, first {nd} of {beam.ndm} DM trials "
+        "sample": f"one beam: {beam.nchan} channels x {beam.nsamp} samples, {what} "
                   f"(Algorithm 1 order, FP32), {el:.1f} s",
         "seconds": el,
     }

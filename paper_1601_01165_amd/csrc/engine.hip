@@ -414,50 +414,87 @@ __device__ __forceinline__ void stage_u8(uint4* lds, const uint8_t* in, const Ti
   }
 }
 
-// Synchronous staging of four byte-shifted copies of each row: copy s holds
-// row[k + s] at position k, so a dword holding four consecutive samples
-// starting at any byte offset o is the aligned dword (o >> 2) of copy o & 3.
-template <int NWAVE, int CC, int ROWCAP>
-__device__ __forceinline__ void stage_u8_shift4(uint4* lds, const uint8_t* in, const TileArgs& a, const int32_t* blk,
-                                                int c0, int ncc, int t0) {
-  const int wave = wave_id(), lane = threadIdx.x & 63;
-  for (int cl = wave; cl < ncc; cl += NWAVE) {
-    const ent2_t bl = sload_entry2(blk + 2 * (c0 + cl));
-    const uint8_t* src = in + (int64_t)(c0 + cl) * a.in_stride;
-    const int u0 = t0 + bl[0];
-    const int nv = bl[1] >> 4;
-    for (int v = lane; v < nv; v += 64) {
-      const int u = u0 + 16 * v;
-      uint32_t d[5];
-      if (u + 20 <= a.in_hi) {
-        const uint4 x = *reinterpret_cast<const uint4*>(src + u);
-        d[0] = x.x;
-        d[1] = x.y;
-        d[2] = x.z;
-        d[3] = x.w;
-        d[4] = *reinterpret_cast<const uint32_t*>(src + u + 16);
-      } else {
+// Staging of four byte-shifted copies of each row: copy s holds row[k + s]
+// at position k, so a dword holding four consecutive samples starting at any
+// byte offset o is the aligned dword (o >> 2) of copy o & 3.  The copies need
+// a byte shift, so the data passes through registers: load() fetches a pass's
+// bytes (and this wave's table entries) into registers, store() writes the
+// shifted copies to LDS.  The kernel calls load() for pass p + 1 before it
+// sums pass p, so the global loads are in flight during the adds.
+template <int NWAVE, int CC, int ROWCAP, typename E>
+struct ShiftStage {
+  static constexpr int RPW = (CC + NWAVE - 1) / NWAVE;  // rows staged per wave
+  static constexpr int VPL = (ROWCAP / 16 + 63) / 64;   // 16-byte chunks per lane per row
+  uint32_t d[RPW][VPL][5];
+  E tab;
+  int nv[RPW];
+
+  __device__ __forceinline__ void load(const uint8_t* in, const TileArgs& a, const int32_t* blk, const int32_t* wav,
+                                       int c0, int ncc, int t0) {
+    const int wave = wave_id(), lane = threadIdx.x & 63;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
-          uint32_t w = 0;
+    for (int r = 0; r < RPW; ++r) {
+      const int cl = wave + r * NWAVE;
+      nv[r] = 0;
+      if (cl < ncc) {
+        const ent2_t bl = sload_entry2(blk + 2 * (c0 + cl));
+        const uint8_t* src = in + (int64_t)(c0 + cl) * a.in_stride;
+        const int u0 = t0 + bl[0];
+        nv[r] = bl[1] >> 4;
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int uu = u + 4 * q + k;
-            w |= (uu < a.in_hi ? (uint32_t)src[uu] : 0u) << (8 * k);
+        for (int i = 0; i < VPL; ++i) {
+          const int v = lane + 64 * i;
+          const int u = u0 + 16 * v;
+          if (v < nv[r]) {
+            if (u + 20 <= a.in_hi) {
+              const uint4 x = *reinterpret_cast<const uint4*>(src + u);
+              d[r][i][0] = x.x;
+              d[r][i][1] = x.y;
+              d[r][i][2] = x.z;
+              d[r][i][3] = x.w;
+              d[r][i][4] = *reinterpret_cast<const uint32_t*>(src + u + 16);
+            } else {
+#pragma unroll
+              for (int q = 0; q < 5; ++q) {
+                uint32_t w = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                  const int uu = u + 4 * q + k;
+                  w |= (uu < a.in_hi ? (uint32_t)src[uu] : 0u) << (8 * k);
+                }
+                d[r][i][q] = w;
+              }
+            }
           }
-          d[q] = w;
         }
       }
-      lds[(0 * CC + cl) * (ROWCAP / 16) + v] = make_uint4(d[0], d[1], d[2], d[3]);
+    }
+    if (lane < ncc) tab = *reinterpret_cast<const E*>(wav + (size_t)(c0 + lane) * (sizeof(E) / 4));
+  }
+
+  __device__ __forceinline__ void store(uint4* lds, E* tabw, int ncc) const {
+    const int wave = wave_id(), lane = threadIdx.x & 63;
 #pragma unroll
-      for (int s = 1; s < 4; ++s) {
-        lds[(s * CC + cl) * (ROWCAP / 16) + v] =
-            make_uint4(__builtin_amdgcn_alignbyte(d[1], d[0], s), __builtin_amdgcn_alignbyte(d[2], d[1], s),
-                       __builtin_amdgcn_alignbyte(d[3], d[2], s), __builtin_amdgcn_alignbyte(d[4], d[3], s));
+    for (int r = 0; r < RPW; ++r) {
+      const int cl = wave + r * NWAVE;
+#pragma unroll
+      for (int i = 0; i < VPL; ++i) {
+        const int v = lane + 64 * i;
+        if (v < nv[r]) {
+          const uint32_t* x = d[r][i];
+          lds[(0 * CC + cl) * (ROWCAP / 16) + v] = make_uint4(x[0], x[1], x[2], x[3]);
+#pragma unroll
+          for (int sh = 1; sh < 4; ++sh) {
+            lds[(sh * CC + cl) * (ROWCAP / 16) + v] =
+                make_uint4(__builtin_amdgcn_alignbyte(x[1], x[0], sh), __builtin_amdgcn_alignbyte(x[2], x[1], sh),
+                           __builtin_amdgcn_alignbyte(x[3], x[2], sh), __builtin_amdgcn_alignbyte(x[4], x[3], sh));
+          }
+        }
       }
     }
+    if (lane < ncc) tabw[lane] = tab;
   }
-}
+};
 
 // Asynchronous staging of one pass: the rows (16-byte buffer loads writing
 // LDS directly; positions past the row end read as zero) and this wave's
@@ -606,7 +643,7 @@ __global__ __launch_bounds__(64 * NWAVE) void u8_kernel(TileArgs a) {
 
 // ---------------------------------------------------------------------------
 // uint8 -> int32 tile engine on byte-shifted rows.  Each input row is staged
-// as four copies shifted by 0..3 bytes (stage_u8_shift4), so the four samples
+// as four copies shifted by 0..3 bytes (ShiftStage), so the four samples
 // a lane needs at any delay are one aligned LDS dword: one 4-byte LDS read
 // per 4 adds.  The table gives, per (wave tile, input row), each output row's
 // dword offset into the staged copies, so a read costs one address add.
@@ -666,13 +703,15 @@ __global__ __launch_bounds__(64 * NWAVE) void u8s_kernel(TileArgs a) {
     s4[3] = (int)(u >> 16);
   };
 
+  ShiftStage<NWAVE, CC, ROWCAP, E> stage;
+  stage.load(in, a, blk, wav, 0, min(CC, a.rows_in), t0);
   for (int p = 0; p < npass; ++p) {
     const int c0 = p * CC;
     const int ncc = min(CC, a.rows_in - c0);
+    __syncthreads();  // every wave is done with pass p - 1's rows
+    stage.store(lds, tab[wave], ncc);
     __syncthreads();
-    stage_u8_shift4<NWAVE, CC, ROWCAP>(lds, in, a, blk, c0, ncc, t0);
-    if (lane < ncc) tab[wave][lane] = *reinterpret_cast<const E*>(wav + (size_t)(c0 + lane) * WI);
-    __syncthreads();
+    if (p + 1 < npass) stage.load(in, a, blk, wav, c0 + CC, min(CC, a.rows_in - c0 - CC), t0);
     for (int cl = 0; cl < ncc; ++cl) {
       const E e = tab[wave][cl];
 #pragma unroll
@@ -822,8 +861,8 @@ __global__ __launch_bounds__(256) void reduce_gradw_kernel(const double* __restr
 // ---------------------------------------------------------------------------
 // (index, TP samples per lane, DPW rows per wave, NWAVE, NWIN window registers,
 //  CC rows per LDS pass, ROWCAP floats per LDS row, NBUF LDS buffers)
-// A lane owns TP consecutive samples; TP/4 odd (12, 20, 28) keeps its 16-byte
-// LDS reads free of bank conflicts.
+// A lane owns TP consecutive samples; TP/4 odd (12, 20, 28, 36) keeps its
+// 16-byte LDS reads free of bank conflicts.
 #define F32_VARIANTS(X)                                          \
   X(0, 12, 4, 4, 36, 8, 1024, 1)   /* 16 DMs x 768             */ \
   X(1, 12, 4, 4, 48, 8, 1024, 1)   /* 16 DMs x 768, wide spans */ \
@@ -841,7 +880,9 @@ __global__ __launch_bounds__(256) void reduce_gradw_kernel(const double* __restr
   X(13, 20, 8, 4, 56, 4, 1536, 2)  /* 32 DMs x 1280, async     */ \
   X(14, 28, 4, 4, 48, 4, 2048, 2)  /* 16 DMs x 1792, async     */ \
   X(15, 20, 8, 8, 56, 4, 1792, 2)  /* 64 DMs x 1280, async     */ \
-  X(16, 28, 4, 8, 48, 4, 2048, 2)  /* 32 DMs x 1792, async     */
+  X(16, 28, 4, 8, 48, 4, 2048, 2)  /* 32 DMs x 1792, async     */ \
+  X(17, 20, 8, 8, 56, 8, 1792, 2)  /* 64 DMs x 1280, async     */ \
+  X(18, 20, 8, 4, 56, 6, 1536, 2)  /* 32 DMs x 1280, async     */
 
 // (index, Q dwords per lane, DPW, NWAVE, CC rows per LDS pass, ROWCAP bytes)
 #define U8_VARIANTS(X)                                      \
@@ -864,7 +905,7 @@ __global__ __launch_bounds__(256) void reduce_gradw_kernel(const double* __restr
   X(13, 2, 4, 8, 4, 1792, false) /* 32 DMs x 512       */   \
   X(14, 4, 2, 4, 4, 1536, false) /*  8 DMs x 1024      */   \
   X(15, 4, 8, 4, 4, 2304, false) /* 32 DMs x 1024      */   \
-  X(16, 2, 4, 4, 4, 1280, false) /* 16 DMs x 512       */   \
+  X(16, 4, 4, 8, 4, 2304, false) /* 32 DMs x 1024      */   \
   X(17, 4, 4, 4, 2, 1792, false) /* 16 DMs x 1024      */   \
   X(18, 4, 4, 4, 4, 1792, true)  /* 16 DMs x 1024, wide */  \
   X(19, 2, 4, 8, 4, 1792, true)  /* 32 DMs x 512, wide  */
