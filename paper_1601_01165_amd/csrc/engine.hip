@@ -302,20 +302,25 @@ __device__ __forceinline__ void win_tile(const TileArgs& a, int tt, int rt, int 
         stage_f32_async<NWAVE, ROWCAP>(lds4 + ((p + 1) & 1) * CC * (ROWCAP / 4), in, a, blk, c0 + CC,
                                        min(CC, a.rows_in - c0 - CC), t0);
     }
-    // two rows per iteration with the entry registers swapping roles, so the
-    // next row's entry needs no copy
     uint32_t row = lane_base + (uint32_t)(bufrow * ROWCAP * 4);
-    int cl = 0;
-    for (; cl + 1 < ncc; cl += 2) {
-      win_step<TP, DPW, NWIN, WEIGHTED>(acc, row + (uint32_t)ea[0] * 4u, ea, eb, trs, toff, wa, wb, wrs, woff);
-      row += ROWCAP * 4;
-      win_step<TP, DPW, NWIN, WEIGHTED>(acc, row + (uint32_t)eb[0] * 4u, eb, ea, trs, toff, wb, wa, wrs, woff);
-      row += ROWCAP * 4;
-    }
-    if (cl < ncc) {
-      win_step<TP, DPW, NWIN, WEIGHTED>(acc, row + (uint32_t)ea[0] * 4u, ea, eb, trs, toff, wa, wb, wrs, woff);
-      ea = eb;
-      wa = wb;
+    if constexpr (HasWinPass<TP, DPW, NWIN, CC>::value) {
+      // the whole pass in one block, index mode on throughout
+      WinPass<TP, DPW, NWIN, CC, WEIGHTED, ROWCAP>::run(acc, row, ncc, ea, trs, toff, wa, wrs, woff);
+    } else {
+      // two rows per iteration with the entry registers swapping roles, so
+      // the next row's entry needs no copy
+      int cl = 0;
+      for (; cl + 1 < ncc; cl += 2) {
+        win_step<TP, DPW, NWIN, WEIGHTED>(acc, row + (uint32_t)ea[0] * 4u, ea, eb, trs, toff, wa, wb, wrs, woff);
+        row += ROWCAP * 4;
+        win_step<TP, DPW, NWIN, WEIGHTED>(acc, row + (uint32_t)eb[0] * 4u, eb, ea, trs, toff, wb, wa, wrs, woff);
+        row += ROWCAP * 4;
+      }
+      if (cl < ncc) {
+        win_step<TP, DPW, NWIN, WEIGHTED>(acc, row + (uint32_t)ea[0] * 4u, ea, eb, trs, toff, wa, wb, wrs, woff);
+        ea = eb;
+        wa = wb;
+      }
     }
   }
 

@@ -136,6 +136,113 @@ def step(tp, dpw, nwin, weighted):
     )
 
 
+SGPR_A = 40  # entry sets of the pass block live in fixed SGPRs from here
+
+
+def pass_block(tp, dpw, nwin, cc, weighted):
+    """Specialisation of WinPass: the rows of one LDS pass in one block with
+    VGPR index mode on throughout (turning it on and off costs about as much
+    as 30 adds; changing the index is nearly free).  Vector instructions other
+    than the adds take their first operand from an SGPR or a literal, so the
+    index does not touch them.  Row r sums from entry set A (r even) or B (r
+    odd), both in fixed SGPRs, and loads the next row's entry into the other
+    set; on exit the next pass's first entry is in A."""
+    nacc = tp * dpw
+    w0 = ACC0 + nacc
+    assert w0 + nwin <= 256
+    nmin = tp // 4 + 1
+    nmax = nwin // 4
+    ent = entry_ints(dpw)
+    sa, sb = SGPR_A, SGPR_A + ent
+    L = ["s_mov_b32 %[m0s], m0", f"s_set_gpr_idx_on s{sa + 2}, gpr_idx(SRC0)"]
+    for r in range(cc):
+        X, Y = (sa, sb) if r % 2 == 0 else (sb, sa)
+        wX, wY = ("%[wa]", "%[wb]") if r % 2 == 0 else ("%[wb]", "%[wa]")
+        L.append(f"s_lshl_b32 %[t], s{X}, 2")
+        L.append("v_add_u32 %[va], %[t], %[vrow]")
+        for k in range(nmin):
+            L.append(f"ds_read_b128 v[{w0 + 4 * k}:{w0 + 4 * k + 3}], %[va] offset:{16 * k}")
+        for k in range(nmin, nmax):
+            L.append(f"s_cmp_le_u32 s{X + 1}, {k}")
+            L.append(f"s_cbranch_scc1 .Lr{r}_loaded_%=")
+            L.append(f"ds_read_b128 v[{w0 + 4 * k}:{w0 + 4 * k + 3}], %[va] offset:{16 * k}")
+        L.append(f".Lr{r}_loaded_%=:")
+        L.append("s_waitcnt lgkmcnt(0)")
+        L.append(f"s_buffer_load_dwordx{ent} s[{Y}:{Y + ent - 1}], %[trs], %[toff]")
+        L.append(f"s_add_u32 %[toff], %[toff], {4 * ent}")
+        if weighted:
+            L.append(f"s_buffer_load_dword {wY}, %[wrs], %[woff]")
+            L.append("s_add_u32 %[woff], %[woff], 4")
+        for j in range(dpw):
+            if not (r == 0 and j == 0):
+                L.append(f"s_set_gpr_idx_idx s{X + 2 + j}")
+            for i in range(tp):
+                a = ACC0 + j * tp + i
+                if weighted:
+                    L.append(f"v_fma_f32 v{a}, v{w0 + i}, {wX}, v{a}")
+                else:
+                    L.append(f"v_add_f32 v{a}, v{w0 + i}, v{a}")
+        L.append("v_add_u32 %[vrow], %[rowbytes], %[vrow]")
+        L.append("s_waitcnt lgkmcnt(0)")
+        if r + 1 < cc:
+            L.append(f"s_cmp_le_u32 %[ncc], {r + 1}")
+            L.append(f"s_cbranch_scc1 {'.Lcopy_%=' if r % 2 == 0 else '.Lend_%='}")
+    if cc % 2 == 0:  # after the last (odd) row the next entry is already in A
+        L.append("s_branch .Lend_%=")
+    L.append(".Lcopy_%=:")
+    for q in range(0, ent, 2):
+        L.append(f"s_mov_b64 s[{sa + q}:{sa + q + 1}], s[{sb + q}:{sb + q + 1}]")
+    if weighted:
+        L.append("s_mov_b32 %[wa], %[wb]")
+    L.append(".Lend_%=:")
+    L.append("s_set_gpr_idx_off")
+    L.append("s_mov_b32 m0, %[m0s]")
+    asm = "".join(f'    "{ln}\\n\\t"\n' for ln in L)
+    etype = f"ent{ent}_t"
+    outs = ['[m0s] "=&s"(m0s)', '[t] "=&s"(t)', '[va] "=&v"(va)', '[vrow] "+v"(vrow)', '[toff] "+s"(toff)',
+            f'[ea] "+{{s[{sa}:{sa + ent - 1}]}}"(ea)', f'[eb] "=&{{s[{sb}:{sb + ent - 1}]}}"(eb)']
+    if weighted:
+        outs += ['[wa] "+s"(wa)', '[wb] "=&s"(wb)', '[woff] "+s"(woff)']
+    for q in range(nacc // 16):
+        lo = ACC0 + 16 * q
+        outs.append(f'[acc{q}] "+{{v[{lo}:{lo + 15}]}}"(acc[{q}])')
+    ins = ['[ncc] "s"(ncc)', '[trs] "s"(trs)', '[rowbytes] "i"(ROWCAP * 4)']
+    if weighted:
+        ins.append('[wrs] "s"(wrs)')
+    clob = [f'"v{w0 + r}"' for r in range(nwin)] + ['"scc"']
+    wflag = "true" if weighted else "false"
+    return (
+        f"template <int ROWCAP>\n"
+        f"struct WinPass<{tp}, {dpw}, {nwin}, {cc}, {wflag}, ROWCAP> {{\n"
+        f"  static __device__ __forceinline__ void run(v16f* acc, uint32_t& vrow, int ncc, {etype}& ea,\n"
+        f"      __amdgpu_buffer_rsrc_t trs, uint32_t& toff, float& wa, __amdgpu_buffer_rsrc_t wrs, uint32_t& woff) {{\n"
+        f"    uint32_t m0s, t, va;\n"
+        f"    {etype} eb;\n"
+        f"    float wb;\n"
+        f"    (void)wa;\n"
+        f"    (void)wb;\n"
+        f"    (void)wrs;\n"
+        f"    (void)woff;\n"
+        f"    asm volatile(\n{asm}"
+        f"      : {', '.join(outs)}\n"
+        f"      : {', '.join(ins)}\n"
+        f"      : {', '.join(clob)});\n"
+        f"  }}\n"
+        f"}};\n"
+    )
+
+
+# (TP, DPW, NWIN, CC) combinations that get a whole-pass block
+PASS_VARIANTS = [
+    (12, 4, 36, 4),
+    (12, 8, 56, 4),
+    (20, 4, 44, 4),
+    (20, 8, 56, 4),
+    (20, 8, 56, 6),
+    (28, 4, 48, 4),
+]
+
+
 def main(out_path):
     parts = [
         "// Generated by gen_win_asm.py: inner step of the register-window kernel.\n",
@@ -163,6 +270,23 @@ def main(out_path):
     for tp, dpw, nwin in VARIANTS:
         for weighted in (False, True):
             parts.append(step(tp, dpw, nwin, weighted))
+            parts.append("\n")
+    parts += [
+        "// Runs the rows of one LDS pass (ncc <= CC rows) with index mode on\n",
+        "// throughout: vrow is this lane's byte address in the pass's first row slot\n",
+        "// (advanced by one row per row), ea the first row's entry on entry and the\n",
+        "// next pass's on exit, wa likewise for the weight.\n",
+        "template <int TP, int DPW, int NWIN, int CC, bool WEIGHTED, int ROWCAP>\n",
+        "struct WinPass;\n",
+        "template <int TP, int DPW, int NWIN, int CC>\n",
+        "struct HasWinPass : std::false_type {};\n",
+    ]
+    for tp, dpw, nwin, cc in PASS_VARIANTS:
+        parts.append(f"template <> struct HasWinPass<{tp}, {dpw}, {nwin}, {cc}> : std::true_type {{}};\n")
+    parts.append("\n")
+    for tp, dpw, nwin, cc in PASS_VARIANTS:
+        for weighted in (False, True):
+            parts.append(pass_block(tp, dpw, nwin, cc, weighted))
             parts.append("\n")
     text = "".join(parts)
     if os.path.exists(out_path) and open(out_path).read() == text:
