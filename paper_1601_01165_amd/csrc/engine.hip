@@ -88,6 +88,17 @@ __device__ __forceinline__ ent16_t sload_entry_t<ent16_t>(const int32_t* p) {
   asm volatile("s_load_dwordx16 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(r) : "s"(p));
   return r;
 }
+// Scalar buffer loads (reads past the resource's range return zero), wait included.
+__device__ __forceinline__ ent8_t sbload8(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  ent8_t r;
+  asm volatile("s_buffer_load_dwordx8 %0, %1, %2\n\ts_waitcnt lgkmcnt(0)" : "=s"(r) : "s"(rs), "s"(off));
+  return r;
+}
+__device__ __forceinline__ ent16_t sbload16(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  ent16_t r;
+  asm volatile("s_buffer_load_dwordx16 %0, %1, %2\n\ts_waitcnt lgkmcnt(0)" : "=s"(r) : "s"(rs), "s"(off));
+  return r;
+}
 __device__ __forceinline__ float sload_f32(const float* p) {
   float r;
   asm volatile("s_load_dword %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(r) : "s"(p));
@@ -423,15 +434,13 @@ __device__ __forceinline__ void stage_u8(uint4* lds, const uint8_t* in, const Ti
 // at position k, so a dword holding four consecutive samples starting at any
 // byte offset o is the aligned dword (o >> 2) of copy o & 3.  The copies need
 // a byte shift, so the data passes through registers: load() fetches a pass's
-// bytes (and this wave's table entries) into registers, store() writes the
-// shifted copies to LDS.  The kernel calls load() for pass p + 1 before it
+// bytes into registers, store() writes the shifted copies to LDS.  The kernel calls load() for pass p + 1 before it
 // sums pass p, so the global loads are in flight during the adds.
 template <int NWAVE, int CC, int ROWCAP, typename E>
 struct ShiftStage {
   static constexpr int RPW = (CC + NWAVE - 1) / NWAVE;  // rows staged per wave
   static constexpr int VPL = (ROWCAP / 16 + 63) / 64;   // 16-byte chunks per lane per row
   uint32_t d[RPW][VPL][5];
-  E tab;
   int nv[RPW];
 
   __device__ __forceinline__ void load(const uint8_t* in, const TileArgs& a, const int32_t* blk, const int32_t* wav,
@@ -474,10 +483,10 @@ struct ShiftStage {
         }
       }
     }
-    if (lane < ncc) tab = *reinterpret_cast<const E*>(wav + (size_t)(c0 + lane) * (sizeof(E) / 4));
+    (void)wav;
   }
 
-  __device__ __forceinline__ void store(uint4* lds, E* tabw, int ncc) const {
+  __device__ __forceinline__ void store(uint4* lds, int ncc) const {
     const int wave = wave_id(), lane = threadIdx.x & 63;
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
@@ -497,7 +506,7 @@ struct ShiftStage {
         }
       }
     }
-    if (lane < ncc) tabw[lane] = tab;
+    (void)ncc;
   }
 };
 
@@ -671,7 +680,6 @@ __global__ __launch_bounds__(64 * NWAVE) void u8s_kernel(TileArgs a) {
   static_assert(256 % CC == 0, "a flush every 256 rows must fall on a pass boundary");
   typedef typename std::conditional<(WI == 4), ent4_t, ent8_t>::type E;
   __shared__ uint4 lds[4 * CC * ROWCAP / 16];
-  __shared__ E tab[NWAVE][CC];
   const int nblk = a.n_time_tiles * a.n_row_tiles;
   const int W = xcd_remap(blockIdx.x, nblk);
   const int tt = W / a.n_row_tiles, rt = W % a.n_row_tiles;
@@ -708,20 +716,39 @@ __global__ __launch_bounds__(64 * NWAVE) void u8s_kernel(TileArgs a) {
     s4[3] = (int)(u >> 16);
   };
 
+  // this wave's table entries, read with scalar loads (past the last row: zero)
+  const __amdgpu_buffer_rsrc_t trs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)wav, (short)0, a.rows_in * WI * 4, 0x00020000);
+  constexpr int NI = CC * WI;  // ints of one pass's entries
+  static_assert(NI == 8 || NI % 16 == 0, "a pass's entries are loaded in 8- or 16-int pieces");
   ShiftStage<NWAVE, CC, ROWCAP, E> stage;
   stage.load(in, a, blk, wav, 0, min(CC, a.rows_in), t0);
   for (int p = 0; p < npass; ++p) {
     const int c0 = p * CC;
     const int ncc = min(CC, a.rows_in - c0);
+    int32_t off[NI];
+    if constexpr (NI == 8) {
+      const ent8_t x = sbload8(trs, (uint32_t)(c0 * WI * 4));
+#pragma unroll
+      for (int k = 0; k < 8; ++k) off[k] = x[k];
+    } else {
+#pragma unroll
+      for (int k0 = 0; k0 < NI; k0 += 16) {
+        const ent16_t x = sbload16(trs, (uint32_t)((c0 * WI + k0) * 4));
+#pragma unroll
+        for (int k = 0; k < 16; ++k) off[k0 + k] = x[k];
+      }
+    }
     __syncthreads();  // every wave is done with pass p - 1's rows
-    stage.store(lds, tab[wave], ncc);
+    stage.store(lds, ncc);
     __syncthreads();
     if (p + 1 < npass) stage.load(in, a, blk, wav, c0 + CC, min(CC, a.rows_in - c0 - CC), t0);
-    for (int cl = 0; cl < ncc; ++cl) {
-      const E e = tab[wave][cl];
+#pragma unroll
+    for (int cl = 0; cl < CC; ++cl) {
+      if (cl >= ncc) break;
 #pragma unroll
       for (int jj = 0; jj < DPW; ++jj) {
-        const uint32_t* pr = lds32 + __builtin_amdgcn_readfirstlane(e[jj]);
+        const uint32_t* pr = lds32 + off[cl * WI + jj];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
           const uint32_t v = pr[64 * q];
