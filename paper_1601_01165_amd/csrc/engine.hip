@@ -935,12 +935,14 @@ __global__ __launch_bounds__(256) void reduce_gradw_kernel(const double* __restr
 #define U8S_VARIANTS(X)                                      \
   X(12, 4, 4, 4, 4, 1792, false) /* 16 DMs x 1024      */   \
   X(13, 2, 4, 8, 4, 1792, false) /* 32 DMs x 512       */   \
-  X(14, 4, 2, 4, 4, 1536, false) /*  8 DMs x 1024      */   \
+  X(14, 4, 4, 8, 8, 2304, false) /* 32 DMs x 1024      */   \
   X(15, 4, 8, 4, 4, 2304, false) /* 32 DMs x 1024      */   \
   X(16, 4, 4, 8, 4, 2304, false) /* 32 DMs x 1024      */   \
   X(17, 4, 4, 4, 2, 1792, false) /* 16 DMs x 1024      */   \
   X(18, 4, 4, 4, 4, 1792, true)  /* 16 DMs x 1024, wide */  \
-  X(19, 2, 4, 8, 4, 1792, true)  /* 32 DMs x 512, wide  */
+  X(19, 4, 4, 8, 4, 2304, true)  /* 32 DMs x 1024, wide */  \
+  X(20, 8, 4, 8, 4, 3328, false) /* 32 DMs x 2048      */   \
+  X(21, 4, 8, 8, 4, 3584, false) /* 64 DMs x 1024      */
 
 const std::vector<Variant>& variants_f32() {
   static const std::vector<Variant> v = [] {
