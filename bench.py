@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the per-beam loop")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-cpu-tuned", action="store_true", help="skip the tuned multi-core CPU comparator")
+    ap.add_argument("--cpu-tuned-seconds", type=float, default=5.0, help="target time of the tuned CPU run")
     ap.add_argument("--beams", type=int, default=0, help="use only the first N beams (debugging)")
     return ap.parse_args()
 
@@ -104,12 +106,13 @@ def cpu_baseline(beam, target_s):
     delta = oracle.delay_table(beam.freqs(), beam.tsamp_s, beam.dms())
     nin = beam.nsamp + int(delta.max())
     x = synth.noise(beam, nin)
+    fwd = oracle.forward_u8 if beam.dtype == "u8" else oracle.forward_f32
     # calibrate on two DM trials per thread (rows are the unit of parallelism)
     nth = max(1, oracle.num_threads())
     ncal = min(beam.ndm, 2 * nth)
-    oracle.forward_f32(x, delta[:nth], beam.nsamp)  # warm threads and caches
+    fwd(x, delta[:nth], beam.nsamp)  # warm threads and caches
     t = time.perf_counter()
-    oracle.forward_f32(x, delta[:ncal], beam.nsamp)
+    fwd(x, delta[:ncal], beam.nsamp)
     dtc = time.perf_counter() - t
     nd = int(ncal * target_s / max(dtc, 1e-6))
     nd = max(nth, nd - nd % nth)
@@ -119,16 +122,59 @@ def cpu_baseline(beam, target_s):
         nd = beam.ndm
     t = time.perf_counter()
     for _ in range(reps):
-        oracle.forward_f32(x, delta[:nd], beam.nsamp)
+        fwd(x, delta[:nd], beam.nsamp)
     el = time.perf_counter() - t
     what = f"first {nd} of {beam.ndm} DM trials" if nd < beam.ndm else f"all {nd} DM trials, {reps} time(s)"
+    arith = "uint8 in, int32 sums" if beam.dtype == "u8" else "FP32"
     return {
         "value": reps * nd * beam.nsamp / el,
         "unit": "DM-trial·samples/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
         "sample": f"one beam: {beam.nchan} channels x {beam.nsamp} samples, {what} "
-                  f"(Algorithm 1 order, FP32), {el:.1f} s",
+                  f"(Algorithm 1 order, {arith}), {el:.1f} s",
+        "seconds": el,
+    }
+
+
+def cpu_tuned(beam, target_s):
+    """Time the tuned multi-core CPU implementation (the paper's CPU
+    comparison, Section 5: tiles of DMs x samples, SIMD over samples, threads
+    over tiles) on one whole beam: its tile shape is tuned first on a 64-DM
+    slice, then the beam is repeated until ~target_s seconds have run.  The
+    output of the first repeat is checked against the oracle on sampled DM
+    trials."""
+    import oracle
+    import synth
+    from paper_1601_01165_amd import cpu
+
+    cpu.build_if_missing()
+    delta = oracle.delay_table(beam.freqs(), beam.tsamp_s, beam.dms())
+    nin = beam.nsamp + int(delta.max())
+    x = synth.noise(beam, nin)[None]
+    times, best = cpu.autotune(x, delta[:64], beam.nsamp, reps=3)
+    t = time.perf_counter()
+    out = cpu.forward(x, delta, beam.nsamp, cfg=best)
+    one = time.perf_counter() - t
+    reps = max(1, int(round(target_s / max(one, 1e-6))))
+    t = time.perf_counter()
+    for _ in range(reps):
+        cpu.forward(x, delta, beam.nsamp, cfg=best, out=out)
+    el = time.perf_counter() - t
+    rows = np.linspace(0, beam.ndm - 1, 4).astype(int)
+    fwd = oracle.forward_u8 if beam.dtype == "u8" else oracle.forward_f32
+    ok = bool(np.array_equal(out[0, rows], fwd(x, delta[rows], beam.nsamp)[0]))
+    dt, ds = cpu.configs()[best]
+    return {
+        "value": reps * beam.ndm * beam.nsamp / el,
+        "unit": "DM-trial·samples/s",
+        "cores": cpu.num_threads(),
+        "kind": "tuned-cpu",
+        "isa": cpu.isa(),
+        "tile": {"dms": dt, "samples": ds},
+        "matches_oracle": ok,
+        "sample": f"one beam: {beam.nchan} channels x {beam.nsamp} samples x {beam.ndm} DM trials, "
+                  f"{reps} time(s), {el:.1f} s",
         "seconds": el,
     }
 
@@ -364,6 +410,11 @@ def main():
         cb_beam = beams[0]
         line["cpu_baseline"] = cpu_baseline(cb_beam, args.cpu_seconds)
         log(f"cpu baseline {line['cpu_baseline']['value']:.3e}")
+    if not args.no_cpu_tuned:
+        log("tuned CPU comparator")
+        line["cpu_tuned"] = cpu_tuned(beams[0], args.cpu_tuned_seconds)
+        line["gpu_over_cpu_tuned"] = value / line["cpu_tuned"]["value"]
+        log(f"tuned cpu {line['cpu_tuned']['value']:.3e}")
     print(json.dumps(line), flush=True)
 
 
