@@ -4,7 +4,9 @@ Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  It shares no code with the GPU library: the arithmetic
 lives in ``dedisp_oracle.c`` (Algorithm 1 of Sclocco et al., arXiv 1601.01165,
 Section 2.1, with the delay law of Section 2, Equation 1) and in the few
-NumPy FP64 helpers below (signal-to-noise and the loss built on it).
+NumPy FP64 helpers below (signal-to-noise, the loss built on it, and the
+boxcar single-pulse search that follows dedispersion in a real-time pipeline,
+Section 1).
 
 Every function cites the passage it follows; see ``dedisp_oracle.c`` for the
 per-function definitions.
@@ -263,3 +265,56 @@ def snr_grad(y) -> np.ndarray:
     dnum[k] += 1.0
     dsd = (y - m) / (n * sd)
     return dnum / sd - num * dsd / (sd * sd)
+
+
+# --------------------------------------------------------------------------
+# Single-pulse search over dedispersed series (the real-time detection that
+# dedispersion feeds, Section 1; the paper does not define it, so the search
+# here is the textbook boxcar matched filter).  FP64, NumPy, one row at a time.
+#
+#   widths      w_k = 2^k for k < nwidth, skipping widths longer than the row
+#   B_w(t)      sum of y[t .. t + w) for 0 <= t <= n - w
+#   mean, std   of the whole row (population std, ddof = 0)
+#   S/N_w       (max_t B_w(t) - w * mean) / (std * sqrt(w)); 0 when std == 0
+#   result      the width with the largest S/N (ties: the narrower), the first
+#               t reaching that width's maximum, its S/N, mean and std
+# --------------------------------------------------------------------------
+
+def boxcar_sums(y, w) -> np.ndarray:
+    """B_w(t) for every full window of the row, each summed directly in FP64."""
+    y = np.asarray(y, np.float64)
+    return np.lib.stride_tricks.sliding_window_view(y, w).sum(axis=1)
+
+
+def detect_row(y, nwidth):
+    """(snr, width, start, mean, std) of one dedispersed series."""
+    y = np.asarray(y, np.float64)
+    n = y.size
+    mean = float(y.mean())
+    std = float(y.std())
+    best = None
+    for k in range(nwidth):
+        w = 1 << k
+        if w > n:
+            break
+        b = boxcar_sums(y, w)
+        t = int(np.argmax(b))
+        s = (float(b[t]) - w * mean) / (std * np.sqrt(w)) if std > 0 else 0.0
+        if best is None or s > best[0]:
+            best = (s, w, t)
+    return best[0], best[1], best[2], mean, std
+
+
+def detect(rows, nwidth):
+    """Search every row of rows [..., nsamp]; returns a dict of arrays of the
+    leading shape: snr (f8), width (i4), start (i4), mean (f8), std (f8)."""
+    rows = np.asarray(rows)
+    lead = rows.shape[:-1]
+    flat = rows.reshape(-1, rows.shape[-1])
+    res = [detect_row(r, nwidth) for r in flat]
+    out = {}
+    for i, (name, dt) in enumerate((("snr", np.float64), ("width", np.int32), ("start", np.int32),
+                                    ("mean", np.float64), ("std", np.float64))):
+        out[name] = np.array([r[i] for r in res], dt).reshape(lead)
+    return out
+
