@@ -193,6 +193,63 @@ int32_t dedisp_batch_variant(dedisp_batch batch);
 dedisp_status dedisp_batch_destroy(dedisp_batch batch);
 
 /* ------------------------------------------------------------------------ */
+/* Single-pulse search (the detection step that dedispersion feeds in the    */
+/* real-time pipeline of Section 1; the paper does not define it, so this is */
+/* the textbook boxcar matched filter)                                       */
+/* ------------------------------------------------------------------------ */
+
+/* For every dedispersed series y = out[b][dm][0 .. nsamp) of dedisp_execute:
+ *   widths    w = 1, 2, 4, ..., 2^(nwidth-1) (1 <= nwidth <= 6), skipping
+ *             widths longer than nsamp
+ *   B_w(t)    = y[t] + ... + y[t + w - 1] for 0 <= t <= nsamp - w
+ *   mean, std of y over its nsamp samples (population std, ddof = 0)
+ *   S/N_w     = (max_t B_w(t) - w * mean) / (std * sqrt(w)), 0 when std == 0
+ * and the result is the width with the largest S/N (ties: the narrower), the
+ * first t where that width's boxcar reaches its maximum, the S/N, mean and
+ * std.  The series themselves are never written to memory: the search runs
+ * in the epilogue of the dedispersion tile kernel (time tiles overlap by the
+ * widest window, so each window lies inside one tile), which leaves one
+ * 64-byte record per (series, tile) in the workspace; a second kernel merges
+ * them.  uint8 input is searched in exact integers (float32 input: boxcar
+ * sums in FP32 by pairwise doubling); moments and S/N are FP64.
+ *   d_in, in_type, in_stride, d_w: as for dedisp_execute
+ *   d_snr    [nbeam][ndm] double        d_width [nbeam][ndm] int32
+ *   d_start  [nbeam][ndm] int32         d_mean, d_std [nbeam][ndm] double, or NULL
+ *   d_workspace: device scratch of at least dedisp_detect_workspace_bytes(...)
+ *            bytes, 16-byte aligned (contents on return: undefined).
+ * Uses a kernel variant with the search in its epilogue: the plan's tuned
+ * variant for in_type when it has one, else the first that fits (see
+ * dedisp_detect_variant); when none fits it dedisperses into the workspace
+ * and searches the stored rows (dedisp_detect_rows).  Asynchronous on
+ * `stream`; the first call of a plan and dtype may build tile tables
+ * (allocates).
+ * Errors: as dedisp_execute, plus DEDISP_E_INVALID (nwidth out of range,
+ * NULL snr/width/start) and DEDISP_E_WORKSPACE (NULL or too small). */
+dedisp_status dedisp_detect(dedisp_plan plan, int32_t nbeam, int32_t nsamp, const void* d_in, dedisp_dtype in_type,
+                            int64_t in_stride, const float* d_w, int32_t nwidth, double* d_snr, int32_t* d_width,
+                            int32_t* d_start, double* d_mean, double* d_std, void* d_workspace,
+                            size_t workspace_bytes, void* stream);
+
+/* Workspace bytes dedisp_detect needs for these sizes with the variant it
+ * would use now (0 for invalid arguments).  May build tile tables. */
+size_t dedisp_detect_workspace_bytes(dedisp_plan plan, dedisp_dtype in_type, int32_t nbeam, int32_t nsamp);
+
+/* The variant dedisp_detect would use for in_type (an index of
+ * dedisp_variant_name(in_type, .)), or -1 for the unfused path. */
+int32_t dedisp_detect_variant(dedisp_plan plan, dedisp_dtype in_type);
+
+/* The same search over nrows stored series d_rows[nrows][stride] (F32, or
+ * I32 searched in float32: exact while every boxcar sum is below 2^24 in
+ * magnitude), with a workspace of dedisp_detect_rows_workspace_bytes(nrows,
+ * nsamp) bytes.  Output arrays are [nrows].  Errors: DEDISP_E_INVALID,
+ * DEDISP_E_DTYPE, DEDISP_E_SHAPE (stride < nsamp), DEDISP_E_ALIGN (row
+ * pointer or row bytes not multiples of 16), DEDISP_E_WORKSPACE. */
+dedisp_status dedisp_detect_rows(int32_t nrows, int32_t nsamp, const void* d_rows, dedisp_dtype type, int64_t stride,
+                                 int32_t nwidth, double* d_snr, int32_t* d_width, int32_t* d_start, double* d_mean,
+                                 double* d_std, void* d_workspace, size_t workspace_bytes, void* stream);
+size_t dedisp_detect_rows_workspace_bytes(int32_t nrows, int32_t nsamp);
+
+/* ------------------------------------------------------------------------ */
 /* Auto-tuning (Section 2.2: tunable work-group and per-thread work sizes,   */
 /* chosen by exhaustive search, Sections 3 and 4.1)                          */
 /* ------------------------------------------------------------------------ */

@@ -27,7 +27,7 @@ from ._clib import F32, I32, U8, DedispError, check
 
 __all__ = [
     "Plan", "Batch", "DedispFunction", "DedispError", "compute_delays", "dedisperse", "dedisperse_autograd",
-    "adjoint", "empty_rows", "variant_names", "lib",
+    "adjoint", "empty_rows", "variant_names", "lib", "detect", "detect_rows",
 ]
 
 
@@ -153,6 +153,11 @@ class Plan:
     def adjoint_variant(self) -> int:
         return int(lib().dedisp_plan_adjoint_variant(self._h))
 
+    def detect_variant(self, dtype="f32") -> int:
+        """Variant with the single-pulse search in its epilogue that detect
+        uses for dtype (-1: the unfused path)."""
+        return int(lib().dedisp_detect_variant(self.handle, _dt(dtype)))
+
     def autotune(self, nbeam: int, nsamp: int, dtype="f32", cache_path: str | None = None) -> dict:
         """Exhaustive search over the compiled variants; returns {name: ms}."""
         L = lib()
@@ -225,6 +230,76 @@ def adjoint(g: torch.Tensor, plan: Plan, nin: int, w: torch.Tensor | None = None
                                ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, nbytes,
                                _stream(gr.device)), "adjoint")
     return gi, gw
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _det_outputs(shape, device):
+    return {"snr": torch.empty(shape, dtype=torch.float64, device=device),
+            "width": torch.empty(shape, dtype=torch.int32, device=device),
+            "start": torch.empty(shape, dtype=torch.int32, device=device),
+            "mean": torch.empty(shape, dtype=torch.float64, device=device),
+            "std": torch.empty(shape, dtype=torch.float64, device=device)}
+
+
+def detect(x: torch.Tensor, plan: Plan, nsamp: int | None = None, w: torch.Tensor | None = None, nwidth: int = 6,
+           workspace: torch.Tensor | None = None) -> dict:
+    """Single-pulse search over every dedispersed series without storing the
+    series: boxcars of widths 1, 2, ..., 2^(nwidth-1); returns tensors
+    [nbeam][ndm] (or [ndm] for 2-D input): snr (f64), width, start (i32),
+    mean, std (f64).  See dedisp_detect in include/dedisp.h."""
+    squeeze = x.dim() == 2
+    xr = _as_rows(x)
+    nb, nc, nin = xr.shape
+    if nc != plan.nchan:
+        raise ValueError(f"input has {nc} channels, plan has {plan.nchan}")
+    if nsamp is None:
+        nsamp = nin - plan.max_delay
+    if nsamp < 1 or nin < nsamp + plan.max_delay:
+        raise ValueError(f"need nin >= nsamp + max_delay ({nsamp} + {plan.max_delay}), got {nin}")
+    dt = _dt(xr.dtype)
+    if w is not None:
+        if dt == U8:
+            raise ValueError("weights are not supported for uint8 input")
+        w = w.detach().to(torch.float32).contiguous()
+        if w.numel() != nc or not w.is_cuda:
+            raise ValueError("weights must be a float32 GPU tensor of nchan values")
+    L = lib()
+    nbytes = L.dedisp_detect_workspace_bytes(plan.handle, dt, nb, nsamp)
+    if workspace is None or workspace.numel() * workspace.element_size() < nbytes:
+        workspace = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=xr.device)
+    o = _det_outputs((nb, plan.ndm), xr.device)
+    check(L.dedisp_detect(plan.handle, nb, nsamp, _ptr(xr), dt, xr.stride(1), _ptr(w), nwidth, _ptr(o["snr"]),
+                          _ptr(o["width"]), _ptr(o["start"]), _ptr(o["mean"]), _ptr(o["std"]), _ptr(workspace),
+                          workspace.numel() * workspace.element_size(), _stream(xr.device)), "detect")
+    return {k: v[0] for k, v in o.items()} if squeeze else o
+
+
+def detect_rows(rows: torch.Tensor, nsamp: int | None = None, nwidth: int = 6) -> dict:
+    """The same search over stored series rows [..., n] (float32, or int32
+    searched in float32); returns tensors of the leading shape."""
+    lead = tuple(rows.shape[:-1])
+    r = _as_rows(rows.reshape(1, -1, rows.shape[-1]))
+    if r.dtype == torch.float32:
+        dt = F32
+    elif r.dtype == torch.int32:
+        dt = I32
+    else:
+        raise ValueError("rows must be float32 or int32")
+    nrows, n = r.shape[1], r.shape[2]
+    nsamp = n if nsamp is None else nsamp
+    if nsamp < 1 or nsamp > n:
+        raise ValueError("need 1 <= nsamp <= row length")
+    L = lib()
+    nbytes = L.dedisp_detect_rows_workspace_bytes(nrows, nsamp)
+    ws = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=r.device)
+    o = _det_outputs((nrows,), r.device)
+    check(L.dedisp_detect_rows(nrows, nsamp, _ptr(r), dt, r.stride(1), nwidth, _ptr(o["snr"]), _ptr(o["width"]),
+                               _ptr(o["start"]), _ptr(o["mean"]), _ptr(o["std"]), _ptr(ws), nbytes,
+                               _stream(r.device)), "detect_rows")
+    return {k: v.reshape(lead) for k, v in o.items()}
 
 
 class DedispFunction(torch.autograd.Function):

@@ -32,7 +32,7 @@ DEVICE_FLAGS = [
     "-Wall", "-Wno-unused-function",
 ]
 
-SOURCES = ["engine.hip", "plan.cpp", "batch.cpp", "tune.cpp"]
+SOURCES = ["engine.hip", "detect.hip", "plan.cpp", "batch.cpp", "tune.cpp", "detect.cpp"]
 
 
 def _gen():

@@ -27,6 +27,7 @@
 //     sequential FP32 loop.
 #include <algorithm>
 
+#include "detect_dev.h"
 #include "internal.h"
 
 namespace dd {
@@ -257,16 +258,79 @@ __device__ __forceinline__ void win_store(const TileArgs& a, const v16f* acc, in
 }
 
 
+// Single-pulse search in place of the store: each wave passes its rows one at
+// a time through its own LDS slot (ST samples plus kDetLook of padding) so
+// that every lane can read its run of TP starts and the kDetLook samples
+// after it; samples past the series end read as -inf.
+template <int TP, int DPW, int NWAVE>
+__device__ __forceinline__ void det_store_f32(const TileArgs& a, const v16f* acc, int tt, int rt, int beam, int t0,
+                                              float4* lds4) {
+  constexpr int ST = 64 * TP;
+  constexpr int DT = NWAVE * DPW;
+  static_assert(TP % 4 == 0, "runs are whole 16-byte chunks");
+  const int wave = wave_id(), lane = threadIdx.x & 63;
+  __syncthreads();  // every wave is done with the staged rows
+  float* slot = reinterpret_cast<float*>(lds4) + wave * (ST + kDetLook);
+  if (lane < kDetLook / 4) reinterpret_cast<float4*>(slot + ST)[lane] = make_float4(-INFINITY, -INFINITY, -INFINITY,
+                                                                                    -INFINITY);
+  const int nvalid = min(ST, a.det_nsamp - t0);
+  const int pos0 = TP * lane;
+  const bool owned = pos0 < a.tile_step;
+  const int lim = nvalid - pos0;
+#pragma unroll
+  for (int jj = 0; jj < DPW; ++jj) {
+    const int r = rt * DT + wave * DPW + jj;
+    if (r >= a.rows_out) break;
+#pragma unroll
+    for (int i4 = 0; i4 < TP / 4; ++i4) {
+      const int e0 = jj * TP + 4 * i4;
+      float4 x;
+      x.x = acc[(e0 + 0) / 16][(e0 + 0) % 16];
+      x.y = acc[(e0 + 1) / 16][(e0 + 1) % 16];
+      x.z = acc[(e0 + 2) / 16][(e0 + 2) % 16];
+      x.w = acc[(e0 + 3) / 16][(e0 + 3) % 16];
+      if (nvalid < ST) {
+        const int p = 4 * i4;
+        x.x = p + 0 < lim ? x.x : -INFINITY;
+        x.y = p + 1 < lim ? x.y : -INFINITY;
+        x.z = p + 2 < lim ? x.z : -INFINITY;
+        x.w = p + 3 < lim ? x.w : -INFINITY;
+      }
+      reinterpret_cast<float4*>(slot + pos0)[i4] = x;
+    }
+    __builtin_amdgcn_wave_barrier();
+    float v[TP + kDetLook];
+#pragma unroll
+    for (int i4 = 0; i4 < (TP + kDetLook) / 4; ++i4) {
+      const float4 x = reinterpret_cast<const float4*>(slot + pos0)[i4];
+      v[4 * i4 + 0] = x.x;
+      v[4 * i4 + 1] = x.y;
+      v[4 * i4 + 2] = x.z;
+      v[4 * i4 + 3] = x.w;
+    }
+    float bval[kDetNW];
+    int bidx[kDetNW];
+    double s1, s2;
+    if (nvalid < ST)
+      det_lane_f32<TP, true>(v, owned, lim, bval, bidx, s1, s2);
+    else
+      det_lane_f32<TP, false>(v, owned, lim, bval, bidx, s1, s2);
+    det_commit_f32(a.det + ((int64_t)beam * a.rows_out + r) * a.n_time_tiles + tt, bval, bidx, s1, s2, pos0, t0);
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // NBUF = 1: synchronous staging through registers, one LDS buffer.
 // NBUF = 2: asynchronous LDS loads into two buffers; the rows of pass p + 1
 // are in flight while pass p is summed.
-template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool WEIGHTED, bool ADJ>
+template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool WEIGHTED, bool ADJ,
+          bool DET = false>
 __device__ __forceinline__ void win_tile(const TileArgs& a, int tt, int rt, int beam, float4* lds4) {
   constexpr int ST = 64 * TP;
   constexpr int DT = NWAVE * DPW;
   constexpr int NACC = TP * DPW / 16;
   constexpr int WI = EntT<DPW>::ints;
-  const int t0 = tt * ST;
+  const int t0 = DET ? tt * a.tile_step : tt * ST;
   const int wave = wave_id(), lane = threadIdx.x & 63;
   const int wt = rt * NWAVE + wave;
   const float* in = static_cast<const float*>(a.in) + (int64_t)beam * a.in_beam_stride;
@@ -335,16 +399,28 @@ __device__ __forceinline__ void win_tile(const TileArgs& a, int tt, int rt, int 
     }
   }
 
-  win_store<TP, DPW, NWAVE, ADJ>(a, acc, tt, rt, beam);
+  if constexpr (DET)
+    det_store_f32<TP, DPW, NWAVE>(a, acc, tt, rt, beam, t0, lds4);
+  else
+    win_store<TP, DPW, NWAVE, ADJ>(a, acc, tt, rt, beam);
 }
 
-template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool WEIGHTED, bool ADJ>
+// LDS of a window kernel: the staged rows, or the search's per-wave series
+// if those need more.
+template <int TP, int NWAVE, int CC, int ROWCAP, int NBUF, bool DET>
+constexpr int win_lds_f4() {
+  return (DET && NWAVE * (64 * TP + kDetLook) > NBUF * CC * ROWCAP) ? NWAVE * (64 * TP + kDetLook) / 4
+                                                                      : NBUF * CC * ROWCAP / 4;
+}
+
+template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool WEIGHTED, bool ADJ,
+          bool DET = false>
 __global__ __launch_bounds__(64 * NWAVE) void win_kernel(TileArgs a) {
-  __shared__ float4 lds4[NBUF * CC * ROWCAP / 4];
+  __shared__ float4 lds4[win_lds_f4<TP, NWAVE, CC, ROWCAP, NBUF, DET>()];
   const int nblk = a.n_time_tiles * a.n_row_tiles;
   const int W = xcd_remap(blockIdx.x, nblk);
-  win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, WEIGHTED, ADJ>(a, W / a.n_row_tiles, W % a.n_row_tiles,
-                                                                   blockIdx.y, lds4);
+  win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, WEIGHTED, ADJ, DET>(a, W / a.n_row_tiles, W % a.n_row_tiles,
+                                                                        blockIdx.y, lds4);
 }
 
 // Persistent form for batches of beams.  The work table is split into one
@@ -671,7 +747,7 @@ __global__ __launch_bounds__(64 * NWAVE) void u8_kernel(TileArgs a) {
 // accept at most 256 input rows.  Sums are exact integers, so the order does
 // not matter.
 // ---------------------------------------------------------------------------
-template <int Q, int DPW, int NWAVE, int CC, int ROWCAP, bool WIDE>
+template <int Q, int DPW, int NWAVE, int CC, int ROWCAP, bool WIDE, bool DET = false>
 __global__ __launch_bounds__(64 * NWAVE) void u8s_kernel(TileArgs a) {
   constexpr int ST = 256 * Q;
   constexpr int DT = NWAVE * DPW;
@@ -679,14 +755,16 @@ __global__ __launch_bounds__(64 * NWAVE) void u8s_kernel(TileArgs a) {
   static_assert(DPW == 2 || DPW == 4 || DPW == 8, "unsupported rows per wave");
   static_assert(256 % CC == 0, "a flush every 256 rows must fall on a pass boundary");
   typedef typename std::conditional<(WI == 4), ent4_t, ent8_t>::type E;
-  __shared__ uint4 lds[4 * CC * ROWCAP / 16];
+  constexpr int LDS_STAGE = 4 * CC * ROWCAP / 16;
+  constexpr int LDS_DET = DET ? NWAVE * (ST + kDetLook) / 4 : 0;
+  __shared__ uint4 lds[LDS_STAGE > LDS_DET ? LDS_STAGE : LDS_DET];
   const int nblk = a.n_time_tiles * a.n_row_tiles;
   const int W = xcd_remap(blockIdx.x, nblk);
   const int tt = W / a.n_row_tiles, rt = W % a.n_row_tiles;
   const int beam = blockIdx.y;
   const int wave = wave_id(), lane = threadIdx.x & 63;
   const int wt = rt * NWAVE + wave;
-  const int t0 = tt * ST;
+  const int t0 = DET ? tt * a.tile_step : tt * ST;
   const uint8_t* in = static_cast<const uint8_t*>(a.in) + (int64_t)beam * a.in_beam_stride;
   const int32_t* blk = uniform_ptr(a.blk + (size_t)rt * a.rows_in * 2);
   const int32_t* __restrict__ wav = uniform_ptr(a.wav + (size_t)wt * a.rows_in * WI);
@@ -769,6 +847,58 @@ __global__ __launch_bounds__(64 * NWAVE) void u8s_kernel(TileArgs a) {
           ev[j][q] = hi[j][q] = 0u;
         }
     }
+  }
+
+  if constexpr (DET) {
+    // Single-pulse search in place of the store (see detect_dev.h): each
+    // wave passes its rows one at a time through its own LDS slot, scaled by
+    // 2^IB for the keys, so every lane reads its L starts and the kDetLook
+    // samples after them.
+    constexpr int L = 4 * Q;
+    constexpr int IB = Q == 2 ? 3 : Q == 4 ? 4 : 5;
+    static_assert((1 << IB) == L, "a lane's run is a power of two");
+    __syncthreads();  // every wave is done with the staged rows
+    int* slot = reinterpret_cast<int*>(lds) + wave * (ST + kDetLook);
+    if (lane < kDetLook / 4) reinterpret_cast<int4*>(slot + ST)[lane] = make_int4(0, 0, 0, 0);
+    const int nvalid = min(ST, a.det_nsamp - t0);
+    const int pos0 = L * lane;
+    const bool owned = pos0 < a.tile_step;
+    const int lim = nvalid - pos0;
+#pragma unroll
+    for (int jj = 0; jj < DPW; ++jj) {
+      const int r = rt * DT + wave * DPW + jj;
+      if (r >= a.rows_out) break;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        int s4[4];
+        if (WIDE) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) s4[e] = acc[WIDE ? jj : 0][WIDE ? q : 0][e];
+        } else {
+          unpack(jj, q, s4);
+        }
+        reinterpret_cast<int4*>(slot)[lane + 64 * q] = make_int4(s4[0] << IB, s4[1] << IB, s4[2] << IB, s4[3] << IB);
+      }
+      __builtin_amdgcn_wave_barrier();
+      int v[L + kDetLook];
+#pragma unroll
+      for (int i4 = 0; i4 < (L + kDetLook) / 4; ++i4) {
+        const int4 x = reinterpret_cast<const int4*>(slot + pos0)[i4];
+        v[4 * i4 + 0] = x.x;
+        v[4 * i4 + 1] = x.y;
+        v[4 * i4 + 2] = x.z;
+        v[4 * i4 + 3] = x.w;
+      }
+      int key[kDetNW];
+      double s1, s2;
+      if (nvalid < ST)
+        det_lane_int<L, IB, true>(v, owned, lim, key, s1, s2);
+      else
+        det_lane_int<L, IB, false>(v, owned, lim, key, s1, s2);
+      det_commit_int<L, IB>(a.det + ((int64_t)beam * a.rows_out + r) * a.n_time_tiles + tt, key, s1, s2, pos0, t0);
+      __builtin_amdgcn_wave_barrier();
+    }
+    return;
   }
 
 #pragma unroll
@@ -1013,6 +1143,50 @@ hipError_t launch_tiled(const Variant& v, const TileArgs& a, int nbeam, bool adj
   }
     U8S_VARIANTS(LAUNCH_U8S)
 #undef LAUNCH_U8S
+  }
+  return hipErrorInvalidDeviceFunction;
+}
+
+// Variants with the single-pulse search in their epilogue: the FP32 window
+// variants from 13 on (asynchronous staging, the fastest ones) and every
+// byte-shifted uint8 variant.
+bool detect_fusable(const Variant& v) {
+  return v.kind == KIND_WIN_F32 ? (v.id >= 13 && v.nbuf == 2) : v.mode >= 1;
+}
+
+int det_step(const Variant& v) {
+  const int run = v.kind == KIND_WIN_F32 ? v.tp : 4 * v.tp;  // window starts per lane
+  return v.st() - run * ((kDetLook - 1 + run - 1) / run);
+}
+
+hipError_t launch_detect(const Variant& v, const TileArgs& a, int nbeam, hipStream_t s) {
+  if (!detect_fusable(v)) return hipErrorInvalidDeviceFunction;
+  const int64_t nblk = (int64_t)a.n_time_tiles * a.n_row_tiles;
+  if (nblk < 1 || nblk > 0x7fffffff || nbeam < 1 || nbeam > 65535) return hipErrorInvalidConfiguration;
+  const dim3 grid((unsigned)nblk, (unsigned)nbeam);
+  const dim3 block(64 * v.nwave);
+  if (v.kind == KIND_WIN_F32) {
+#define LAUNCH_DF(ID, TP, DPW, NW, NWIN, CC, RC, NB)                                                          \
+  if constexpr (ID >= 13 && NB == 2) {                                                                        \
+    if (v.id == ID) {                                                                                         \
+      if (a.w_in)                                                                                             \
+        hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, true, false, true>), grid, block, 0, s, a); \
+      else                                                                                                    \
+        hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, false, false, true>), grid, block, 0, s,  \
+                           a);                                                                                \
+      return hipGetLastError();                                                                               \
+    }                                                                                                         \
+  }
+    F32_VARIANTS(LAUNCH_DF)
+#undef LAUNCH_DF
+  } else {
+#define LAUNCH_DU8(ID, Q, DPW, NW, CC, RC, WIDE)                                          \
+  if (v.id == ID) {                                                                       \
+    hipLaunchKernelGGL((u8s_kernel<Q, DPW, NW, CC, RC, WIDE, true>), grid, block, 0, s, a); \
+    return hipGetLastError();                                                             \
+  }
+    U8S_VARIANTS(LAUNCH_DU8)
+#undef LAUNCH_DU8
   }
   return hipErrorInvalidDeviceFunction;
 }

@@ -70,6 +70,21 @@ struct Tables {
   size_t bytes = 0;
 };
 
+// Single-pulse search (detect_dev.h): boxcar widths 1, 2, ..., 2^(kDetNW - 1);
+// each lane reads kDetLook samples past its run of window starts.
+constexpr int kDetNW = 6;
+constexpr int kDetLook = 32;
+
+// One record per (series, time tile): per width the largest window sum
+// (int32 for uint8 input, float bits otherwise) and its first start (-1: no
+// window), and the FP64 sum and sum of squares of the tile's owned samples.
+struct DetRec {
+  int32_t val[kDetNW];
+  int32_t pos[kDetNW];
+  double s1, s2;
+};
+static_assert(sizeof(DetRec) == 64, "records are 64 bytes");
+
 // Arguments of the tiled kernels (passed by value).
 struct TileArgs {
   const void* in;            // input rows of beam 0
@@ -95,6 +110,10 @@ struct TileArgs {
   int64_t x_stride;
   int64_t x_beam_stride;
   double* partial;           // [beam][n_time_tiles][rows_out]
+  // single-pulse search launches only
+  int tile_step;             // samples between time tiles = window starts owned by a tile
+  int det_nsamp;             // samples of each dedispersed series
+  DetRec* det;               // [beam][rows_out][n_time_tiles]
 };
 
 // One beam of a batched launch.
@@ -124,6 +143,22 @@ constexpr int kCounterStride = 32;
 hipError_t launch_batched(const Variant& v, const BeamDesc* d_beams, bool weighted, const int32_t* d_order,
                           const int32_t* d_qoff, int* d_counter, int grid, hipStream_t s);
 hipError_t launch_zero_counter(int* d_counter, hipStream_t s);
+
+// Single-pulse search.  detect_fusable: the variant has a kernel with the
+// search in its epilogue; det_step: window starts owned by one of its time
+// tiles (its tile length minus the lane runs that cover kDetLook - 1 samples).
+bool detect_fusable(const Variant& v);
+int det_step(const Variant& v);
+hipError_t launch_detect(const Variant& v, const TileArgs& a, int nbeam, hipStream_t s);
+// Unfused search over stored rows (float32, or int32 searched in float32).
+constexpr int kDetRowsRun = 16;                              // starts per lane
+constexpr int kDetRowsTile = 64 * kDetRowsRun;               // samples per tile
+constexpr int kDetRowsStep = kDetRowsTile - 2 * kDetRowsRun;  // owned starts per tile
+hipError_t launch_detect_rows(const void* rows, bool i32, int64_t stride, int nrows, int nsamp, int ntiles,
+                              DetRec* recs, hipStream_t s);
+// Merge the records of each series (tile order) into its result.
+hipError_t launch_det_finish(const DetRec* recs, bool int_vals, int nseries, int ntiles, int nsamp, int nwidth,
+                             double* snr, int32_t* width, int32_t* start, double* mean, double* stdv, hipStream_t s);
 int batched_blocks_per_cu(const Variant& v);
 
 // Timing (tune.cpp): median of `reps` launches of fn after a warm-up launch,

@@ -117,3 +117,32 @@ def test_null_handles_are_rejected(clib):
     f = np.array([1400.0])
     assert clib.dedisp_plan_create(ctypes.byref(h), 0, f.ctypes.data, 1.0, 1, f.ctypes.data) == _clib.E_INVALID
     assert not h.value
+
+
+def test_detect_argument_checks(clib):
+    # every check below fails before any device work
+    from paper_1601_01165_amd import _clib
+
+    E = _clib
+    assert clib.dedisp_detect(None, 1, 1, None, 0, 1, None, 6, None, None, None, None, None, None, 0, None) == E.E_INVALID
+    assert clib.dedisp_detect_workspace_bytes(None, 0, 1, 1) == 0
+    assert clib.dedisp_detect_variant(None, 0) == -1
+    assert clib.dedisp_detect_rows_workspace_bytes(0, 10) == 0
+    # 3 rows of 2000 samples: two 992-start tiles and a partial one, 64-byte records
+    assert clib.dedisp_detect_rows_workspace_bytes(3, 2000) == 3 * 3 * 64
+    p = ctypes.c_void_p(4096)  # never dereferenced: the checks fail first
+    def rows(n, ns, dt, stride, nw, snr=p, ws=p, wsb=1 << 20, rowp=p):
+        return clib.dedisp_detect_rows(n, ns, rowp, dt, stride, nw, snr, p, p, None, None, ws, wsb, None)
+    assert rows(0, 10, E.F32, 12, 6) == E.E_INVALID
+    assert rows(2, 0, E.F32, 12, 6) == E.E_INVALID
+    assert rows(2, 10, E.F32, 12, 6, rowp=None) == E.E_INVALID
+    assert rows(2, 10, E.F32, 12, 0) == E.E_INVALID
+    assert rows(2, 10, E.F32, 12, 7) == E.E_INVALID
+    assert rows(2, 10, E.F32, 12, 6, snr=None) == E.E_INVALID
+    assert rows(2, 10, E.U8, 16, 6) == E.E_DTYPE
+    assert rows(2, 10, E.F32, 8, 6) == E.E_SHAPE
+    assert rows(2, 10, E.F32, 10, 6) == E.E_ALIGN
+    assert rows(2, 10, E.F32, 12, 6, rowp=ctypes.c_void_p(4100)) == E.E_ALIGN
+    assert rows(2, 10, E.F32, 12, 6, ws=None) == E.E_WORKSPACE
+    assert rows(2, 10, E.F32, 12, 6, ws=ctypes.c_void_p(4104)) == E.E_ALIGN
+    assert rows(2, 10, E.F32, 12, 6, wsb=64) == E.E_WORKSPACE
