@@ -39,7 +39,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batched", choices=["batched", "apertif", "lofar", "diff", "copy"],
+    ap.add_argument("--workload", default="batched",
+                    choices=["batched", "apertif", "lofar", "diff", "detect_apertif", "detect_lofar", "copy"],
                     help="copy: a plain 1 GiB device copy, the reference for HBM byte counters")
     ap.add_argument("--no-tune", action="store_true", help="use default variants (no autotuning)")
     ap.add_argument("--variant", type=int, default=None, help="force a kernel variant (no autotuning)")
@@ -96,9 +97,11 @@ def time_steps(fn, steps, warmup, stream_sync):
     return total_ms / steps, launch_ms, wall
 
 
-def cpu_baseline(beam, target_s):
+def cpu_baseline(beam, target_s, search=False):
     """Time the plain oracle on a bounded sample of one beam: all channels and
-    samples, a prefix of the DM trials sized for ~target_s seconds."""
+    samples, a prefix of the DM trials sized for ~target_s seconds (with
+    search: each dedispersed series also goes through the oracle's boxcar
+    search)."""
     import oracle
     import synth
 
@@ -106,7 +109,13 @@ def cpu_baseline(beam, target_s):
     delta = oracle.delay_table(beam.freqs(), beam.tsamp_s, beam.dms())
     nin = beam.nsamp + int(delta.max())
     x = synth.noise(beam, nin)
-    fwd = oracle.forward_u8 if beam.dtype == "u8" else oracle.forward_f32
+    fwd0 = oracle.forward_u8 if beam.dtype == "u8" else oracle.forward_f32
+
+    def fwd(x, d, n):
+        y = fwd0(x, d, n)
+        if search:
+            oracle.detect(y, 6)
+        return y
     # calibrate on two DM trials per thread (rows are the unit of parallelism)
     nth = max(1, oracle.num_threads())
     ncal = min(beam.ndm, 2 * nth)
@@ -126,6 +135,8 @@ def cpu_baseline(beam, target_s):
     el = time.perf_counter() - t
     what = f"first {nd} of {beam.ndm} DM trials" if nd < beam.ndm else f"all {nd} DM trials, {reps} time(s)"
     arith = "uint8 in, int32 sums" if beam.dtype == "u8" else "FP32"
+    if search:
+        arith += ", then the FP64 boxcar search of widths 1..32"
     return {
         "value": reps * nd * beam.nsamp / el,
         "unit": "DM-trial·samples/s",
@@ -242,8 +253,8 @@ def main():
         copy_calibration(args, torch, sync)
         return
     extra = {}
-    if wl in ("batched", "apertif", "diff"):
-        k = {"batched": 3, "apertif": 1, "diff": 4}[wl]
+    if wl in ("batched", "apertif", "diff", "detect_apertif"):
+        k = {"batched": 3, "apertif": 1, "diff": 4, "detect_apertif": 1}[wl]
     else:
         k = 2
     beams = synth.config(k)
@@ -320,6 +331,48 @@ def main():
         variant_name = dd.variant_names(dt)[vi] if vi >= 0 else "direct"
         kernel_name = ("direct_u8_kernel" if dt == "u8" else "direct_f32_kernel") if vi < 0 else \
             ("u8s_kernel" if variant_name.startswith("u8s_") else "u8_kernel" if dt == "u8" else "win_kernel")
+    elif wl in ("detect_apertif", "detect_lofar"):
+        # single-pulse search fused into the dedispersion epilogue (boxcar
+        # widths 1..32), the unfused path (store, then search) timed beside it
+        p, b, x, o = plans[0], beams[0], xs[0], outs[0]
+        dt = "u8" if b.dtype == "u8" else "f32"
+        ws = torch.empty(max(1, dd.lib().dedisp_detect_workspace_bytes(p.handle, dd._dt(dt), 1, b.nsamp) * 2),
+                         dtype=torch.uint8, device=dev)
+        if args.variant is not None:
+            p.set_variant(args.variant, dt)
+        elif not args.no_tune:
+            # forward variant for the unfused path, then the fastest fused variant
+            p.autotune(1, b.nsamp, dt)
+            fwd = p.variant(dt)
+            cand = {}
+            for i in range(len(dd.variant_names(dt))):
+                try:
+                    p.set_variant(i, dt)
+                except dd.DedispError:
+                    continue
+                if p.detect_variant(dt) != i:
+                    continue
+                t_ms, _, _ = time_steps(lambda: dd.detect(x, p, nsamp=b.nsamp, workspace=ws), 3, 1, sync)
+                cand[i] = t_ms
+            extra["detect_tune_ms"] = {dd.variant_names(dt)[i]: round(v, 4) for i, v in cand.items()}
+            log(f"fused variants: {extra['detect_tune_ms']}")
+            p.set_variant(fwd, dt)
+            ms_u, _, _ = time_steps(lambda: (dd.dedisperse(x, p, nsamp=b.nsamp, out=o), dd.detect_rows(o)),
+                                    args.steps, args.warmup, sync)
+            extra["unfused_ms_per_step"] = ms_u
+            extra["unfused_forward_variant"] = dd.variant_names(dt)[fwd] if fwd >= 0 else "direct"
+            log(f"unfused (store, then search): {ms_u:.3f} ms/step")
+            if cand:
+                p.set_variant(min(cand, key=cand.get), dt)
+        vi = p.detect_variant(dt)
+        variant_name = dd.variant_names(dt)[vi] if vi >= 0 else "unfused"
+        # algorithmic bytes: input once, delay table, the per-tile records and the results (no series)
+        rec = dd.lib().dedisp_detect_workspace_bytes(p.handle, dd._dt(dt), 1, b.nsamp)
+        algo_bytes = b.nchan * x.shape[2] * b.elem_bytes() + 4 * b.nchan * b.ndm + rec + 32 * b.ndm
+
+        def step():
+            dd.detect(x, p, nsamp=b.nsamp, workspace=ws)
+        kernel_name = ("u8s_kernel" if dt == "u8" else "win_kernel") + " with the search epilogue + det_finish_kernel"
     else:  # diff: forward + adjoint with the weight gradient over all beams
         w = torch.ones(beams[0].nchan, device=dev)
         p0 = plans[0]
@@ -362,6 +415,11 @@ def main():
         roof.update({"bound": "hbm", "achieved": algo_bytes / (kern_ms / 1e3) / 1e9, "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": algo_bytes / (kern_ms / 1e3) / HBM_PEAK,
                      "note": "algorithmic bytes: input once + int32 output + delay table"})
+    if wl.startswith("detect_"):
+        roof["note"] = ("the paper's dedispersion adds only (one per channel, DM trial and sample); the search's "
+                        "own integer/FP32 work is not counted; kernel_ms covers the tile kernel and the record merge")
+        if "unfused_ms_per_step" in extra:
+            extra["fused_over_unfused"] = extra["unfused_ms_per_step"] / ms
     roof["traffic"] = stored_traffic(wl, variant_name)
     roof["algorithmic_bytes"] = algo_bytes
     line = {
@@ -375,7 +433,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u8" if wl == "lofar" else "f32",
+        "dtype": "u8" if wl in ("lofar", "detect_lofar") else "f32",
         "data": "synthetic",
         "config": {
             "workload": {
@@ -384,6 +442,10 @@ def main():
                 "apertif": "Apertif-like beam: 1024 ch 1270-1570 MHz, 2048 DMs step 0.25, 20000 samples, FP32",
                 "lofar": "LOFAR-like beam: 32 ch 134.875-141.125 MHz, 2048 DMs step 0.01, 200000 samples, u8->i32",
                 "diff": "32 Apertif-like beams, 1024 ch, 1024 DMs, 20000 samples: forward + adjoint + grad_w",
+                "detect_apertif": "Apertif-like beam (as apertif) dedispersed and searched with boxcars of 1..32 "
+                                  "samples in one pass, series never stored",
+                "detect_lofar": "LOFAR-like beam (as lofar) dedispersed and searched with boxcars of 1..32 "
+                                "samples in one pass, series never stored",
             }[wl],
             "beams": len(beams),
             "dm_trial_samples_per_step": dm_samples,
@@ -408,9 +470,9 @@ def main():
     if not args.no_cpu:
         log("CPU oracle baseline")
         cb_beam = beams[0]
-        line["cpu_baseline"] = cpu_baseline(cb_beam, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(cb_beam, args.cpu_seconds, search=wl.startswith("detect_"))
         log(f"cpu baseline {line['cpu_baseline']['value']:.3e}")
-    if not args.no_cpu_tuned:
+    if not args.no_cpu_tuned and not wl.startswith("detect_"):
         log("tuned CPU comparator")
         line["cpu_tuned"] = cpu_tuned(beams[0], args.cpu_tuned_seconds)
         line["gpu_over_cpu_tuned"] = value / line["cpu_tuned"]["value"]

@@ -10,8 +10,8 @@
 namespace dd {
 
 // One wave per row and time tile; each lane loads its run of kDetRowsRun
-// starts and the kDetLook samples after it straight from memory (neighbouring
-// lanes' loads overlap and hit the cache), -inf past the row end.
+// starts (-inf past the row end) and takes the look-ahead from the lanes
+// above.
 template <bool I32>
 __global__ __launch_bounds__(256) void detect_rows_kernel(const void* __restrict__ rows, int64_t stride, int nrows,
                                                           int nsamp, int ntiles, DetRec* __restrict__ recs) {
@@ -24,13 +24,14 @@ __global__ __launch_bounds__(256) void detect_rows_kernel(const void* __restrict
   const int t0 = tt * kDetRowsStep;
   const int nvalid = min(ST, nsamp - t0);
   const int pos0 = L * lane;
-  const int lim = nvalid - pos0;
+  const int lim = nvalid - pos0;    // the lane's starts that hold samples
+  const int avail = nsamp - t0 - pos0;  // samples of the row from the lane's first start on
   float v[L + kDetLook];
   if (I32) {
     const int32_t* src = static_cast<const int32_t*>(rows) + (int64_t)r * stride + t0 + pos0;
-    if (lim >= L + kDetLook) {
+    if (avail >= L) {
 #pragma unroll
-      for (int i4 = 0; i4 < (L + kDetLook) / 4; ++i4) {
+      for (int i4 = 0; i4 < L / 4; ++i4) {
         const int4 x = reinterpret_cast<const int4*>(src)[i4];
         v[4 * i4 + 0] = (float)x.x;
         v[4 * i4 + 1] = (float)x.y;
@@ -39,13 +40,13 @@ __global__ __launch_bounds__(256) void detect_rows_kernel(const void* __restrict
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < L + kDetLook; ++i) v[i] = i < lim ? (float)src[i] : -INFINITY;
+      for (int i = 0; i < L; ++i) v[i] = i < avail ? (float)src[i] : -INFINITY;
     }
   } else {
     const float* src = static_cast<const float*>(rows) + (int64_t)r * stride + t0 + pos0;
-    if (lim >= L + kDetLook) {
+    if (avail >= L) {
 #pragma unroll
-      for (int i4 = 0; i4 < (L + kDetLook) / 4; ++i4) {
+      for (int i4 = 0; i4 < L / 4; ++i4) {
         const float4 x = reinterpret_cast<const float4*>(src)[i4];
         v[4 * i4 + 0] = x.x;
         v[4 * i4 + 1] = x.y;
@@ -54,7 +55,7 @@ __global__ __launch_bounds__(256) void detect_rows_kernel(const void* __restrict
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < L + kDetLook; ++i) v[i] = i < lim ? src[i] : -INFINITY;
+      for (int i = 0; i < L; ++i) v[i] = i < avail ? src[i] : -INFINITY;
     }
   }
   float bval[kDetNW];

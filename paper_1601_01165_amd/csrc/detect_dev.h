@@ -16,7 +16,7 @@
 // width the largest sum and its first start, plus the FP64 sum and sum of
 // squares of its owned samples.  A second kernel merges the records of a
 // series in tile order.  In a tile each lane owns a run of L consecutive
-// starts and reads the 32 samples after its run as look-ahead.
+// starts and takes the 32 samples after its run from the lanes above.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,42 +26,92 @@
 
 namespace dd {
 
-// Sum of a double over the 64 lanes of a wave (fixed butterfly order; lane 0
-// holds the same value on every run).
-__device__ __forceinline__ double det_wave_sum(double x) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
-  return x;
+// Reductions over the 64 lanes of a wave with DPP row shifts and row
+// broadcasts (no LDS traffic): shifts by 1, 2, 4 and 8 lanes leave each
+// 16-lane row's result in its lane 15, broadcasting lane 15 into rows 1 and 3
+// and then lane 31 into rows 2 and 3 leaves the wave's result in lane 63,
+// which is read as a scalar.  Lanes whose DPP source is out of range or
+// masked take `old`: the value itself for max/min, zero for sums.  The
+// order of the additions is fixed, so sums are reproducible.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int det_dpp(int old, int x) {
+  return __builtin_amdgcn_update_dpp(old, x, CTRL, ROWMASK, 0xf, false);
 }
+
+#define DET_WAVE_REDUCE(OP, OLD)                   \
+  x = OP(x, det_dpp<0x111, 0xf>(OLD, x));          \
+  x = OP(x, det_dpp<0x112, 0xf>(OLD, x));          \
+  x = OP(x, det_dpp<0x114, 0xf>(OLD, x));          \
+  x = OP(x, det_dpp<0x118, 0xf>(OLD, x));          \
+  x = OP(x, det_dpp<0x142, 0xa>(OLD, x));          \
+  x = OP(x, det_dpp<0x143, 0xc>(OLD, x));
+
+__device__ __forceinline__ int det_imax(int a, int b) { return max(a, b); }
+__device__ __forceinline__ int det_imin(int a, int b) { return min(a, b); }
+__device__ __forceinline__ int det_iadd(int a, int b) { return a + b; }
 
 __device__ __forceinline__ int det_wave_max(int x) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) x = max(x, __shfl_xor(x, m, 64));
-  return x;
-}
-
-__device__ __forceinline__ float det_wave_maxf(float x) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) x = fmaxf(x, __shfl_xor(x, m, 64));
-  return x;
+  DET_WAVE_REDUCE(det_imax, x)
+  return __builtin_amdgcn_readlane(x, 63);
 }
 
 __device__ __forceinline__ int det_wave_min(int x) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) x = min(x, __shfl_xor(x, m, 64));
-  return x;
+  DET_WAVE_REDUCE(det_imin, x)
+  return __builtin_amdgcn_readlane(x, 63);
 }
 
-// Float series.  v[0 .. L + 32) holds the lane's run and its look-ahead, with
-// -inf at positions past the end of the series, so a window that reaches
-// them sums to -inf and never wins.  Boxcar sums by doubling,
-// B_2w(i) = B_w(i) + B_w(i + w), the order the record merge and the unfused
-// search share.  owned: the lane's starts belong to this tile; lim: starts
-// i < lim hold samples of the series (MASK = false when lim >= L).  Per width
-// the lane's largest sum and its first start (-1 and -inf when none).
+__device__ __forceinline__ int det_wave_sum_i(int x) {
+  DET_WAVE_REDUCE(det_iadd, 0)
+  return __builtin_amdgcn_readlane(x, 63);
+}
+
+__device__ __forceinline__ int det_fmax_bits(int a, int b) {
+  return __float_as_int(fmaxf(__int_as_float(a), __int_as_float(b)));
+}
+
+__device__ __forceinline__ float det_wave_maxf(float xf) {
+  int x = __float_as_int(xf);
+  DET_WAVE_REDUCE(det_fmax_bits, x)
+  return __int_as_float(__builtin_amdgcn_readlane(x, 63));
+}
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double det_dpp_d(double x) {
+  const int lo = det_dpp<CTRL, ROWMASK>(0, __double2loint(x));
+  const int hi = det_dpp<CTRL, ROWMASK>(0, __double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double det_wave_sum(double x) {
+  x += det_dpp_d<0x111, 0xf>(x);
+  x += det_dpp_d<0x112, 0xf>(x);
+  x += det_dpp_d<0x114, 0xf>(x);
+  x += det_dpp_d<0x118, 0xf>(x);
+  x += det_dpp_d<0x142, 0xa>(x);
+  x += det_dpp_d<0x143, 0xc>(x);
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), 63),
+                          __builtin_amdgcn_readlane(__double2loint(x), 63));
+}
+
+// The lane one higher's copy of x (DPP wave shift); lane 63 gets `old`.
+__device__ __forceinline__ int det_next_lane(int old, int x) {
+  return __builtin_amdgcn_update_dpp(old, x, 0x130, 0xf, 0xf, false);
+}
+
+// Float series.  v[0 .. L) holds the lane's run; the look-ahead v[L .. L + 32)
+// is filled from the lanes above (position L + k of this lane is position k
+// of the next lane), lane 63's from -inf.  Positions past the end of the
+// series must hold -inf, so a window that reaches them sums to -inf and
+// never wins.  Boxcar sums by doubling, B_2w(i) = B_w(i) + B_w(i + w).
+// owned: the lane's starts belong to this tile; lim: starts i < lim hold
+// samples of the series (MASK = false when lim >= L).  Per width the lane's
+// largest sum and its first start (-inf and -1 when none).
 template <int L, bool MASK>
 __device__ __forceinline__ void det_lane_f32(float* v, bool owned, int lim, float* bval, int* bidx, double& s1,
                                              double& s2) {
+#pragma unroll
+  for (int j = L; j < L + kDetLook; ++j)
+    v[j] = __int_as_float(det_next_lane(__float_as_int(-INFINITY), __float_as_int(v[j - L])));
   s1 = 0.0;
   s2 = 0.0;
 #pragma unroll
@@ -131,14 +181,19 @@ __device__ __forceinline__ void det_commit_f32(DetRec* rec, const float* bval, c
   }
 }
 
-// Integer series (uint8 input: exact sums).  v[0 .. L + 32) holds the run and
-// look-ahead scaled by 2^IB (y << IB).  With prefix sums P over v, the key
-//   P(i + w) - (P(i) - (L - 1 - i)) = (B_w(i) << IB) + (L - 1 - i)
+// Integer series (uint8 input: exact sums).  v[0 .. L) holds the lane's run
+// scaled by 2^IB (y << IB).  With E(j) the sum of the first j values from the
+// lane's first start on (its own prefix for j <= L, then E(j) = E(L) + the
+// next lane's E(j - L)), the key
+//   E(i + w) - (E(i) - (L - 1 - i)) = (B_w(i) << IB) + (L - 1 - i)
 // orders windows by sum and, for equal sums, the earlier start first, so one
 // integer max per window finds both.  Starts outside the tile's owned range
-// or past the series end get P(i) := 2^30 and prefix entries past the end
-// -2^30, which makes every key that touches them negative (the host limits
-// sums to keep |P| < 2^30).  Per width the lane's largest key (negative: none).
+// or past the series end get E(i) := 2^30, entries past the end -2^30, which
+// makes every key that touches them negative (the host limits sums to keep
+// |E| < 2^30).  One pass in order of j: E(j) closes the window of width w
+// that starts at j - w, so only the L start terms and the entries the next
+// look-ahead step reads stay live.  Per width the lane's largest key
+// (negative: none).
 template <int L, int IB, bool MASK>
 __device__ __forceinline__ void det_lane_int(const int* v, bool owned, int lim, int* key, double& s1, double& s2) {
   int s1i = 0;
@@ -155,24 +210,24 @@ __device__ __forceinline__ void det_lane_int(const int* v, bool owned, int lim, 
   if (!owned) s2 = 0.0;
 #pragma unroll
   for (int k = 0; k < kDetNW; ++k) key[k] = INT32_MIN;
-  // One pass over the prefix sums P(j), j = 0 .. L + 31: P(j) closes the
-  // window of width w that starts at j - w, so only the L start terms stay
-  // live, not the whole prefix.
+  int E[L + kDetLook];
   int Q[L];
-  int P = 0;
+  E[0] = 0;
 #pragma unroll
   for (int j = 0; j < L + kDetLook; ++j) {
+    if (j > 0) {
+      const int e = j <= L ? E[j - 1] + v[j - 1] : E[L] + det_next_lane(0, E[j - L]);
+      E[j] = (MASK && j > lim) ? -(1 << 30) : e;
+    }
     if (j < L) {
       const bool start_ok = owned && (!MASK || j < lim);
-      Q[j] = start_ok ? P - (L - 1 - j) : (1 << 30);
+      Q[j] = start_ok ? E[j] - (L - 1 - j) : (1 << 30);
     }
-    const int Pj = (MASK && j > lim) ? -(1 << 30) : P;
 #pragma unroll
     for (int k = 0; k < kDetNW; ++k) {
       const int i = j - (1 << k);
-      if (i >= 0 && i < L) key[k] = max(key[k], Pj - Q[i]);
+      if (i >= 0 && i < L) key[k] = max(key[k], E[j] - Q[i]);
     }
-    if (j + 1 < L + kDetLook) P += v[j];
   }
 }
 

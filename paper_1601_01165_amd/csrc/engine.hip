@@ -258,21 +258,15 @@ __device__ __forceinline__ void win_store(const TileArgs& a, const v16f* acc, in
 }
 
 
-// Single-pulse search in place of the store: each wave passes its rows one at
-// a time through its own LDS slot (ST samples plus kDetLook of padding) so
-// that every lane can read its run of TP starts and the kDetLook samples
-// after it; samples past the series end read as -inf.
+// Single-pulse search in place of the store: each lane's TP consecutive
+// samples of a row are its run of window starts; the look-ahead comes from
+// the lanes above (DPP), so the rows never leave the registers.  Samples past
+// the series end read as -inf.
 template <int TP, int DPW, int NWAVE>
-__device__ __forceinline__ void det_store_f32(const TileArgs& a, const v16f* acc, int tt, int rt, int beam, int t0,
-                                              float4* lds4) {
+__device__ __forceinline__ void det_store_f32(const TileArgs& a, const v16f* acc, int tt, int rt, int beam, int t0) {
   constexpr int ST = 64 * TP;
   constexpr int DT = NWAVE * DPW;
-  static_assert(TP % 4 == 0, "runs are whole 16-byte chunks");
   const int wave = wave_id(), lane = threadIdx.x & 63;
-  __syncthreads();  // every wave is done with the staged rows
-  float* slot = reinterpret_cast<float*>(lds4) + wave * (ST + kDetLook);
-  if (lane < kDetLook / 4) reinterpret_cast<float4*>(slot + ST)[lane] = make_float4(-INFINITY, -INFINITY, -INFINITY,
-                                                                                    -INFINITY);
   const int nvalid = min(ST, a.det_nsamp - t0);
   const int pos0 = TP * lane;
   const bool owned = pos0 < a.tile_step;
@@ -281,42 +275,20 @@ __device__ __forceinline__ void det_store_f32(const TileArgs& a, const v16f* acc
   for (int jj = 0; jj < DPW; ++jj) {
     const int r = rt * DT + wave * DPW + jj;
     if (r >= a.rows_out) break;
-#pragma unroll
-    for (int i4 = 0; i4 < TP / 4; ++i4) {
-      const int e0 = jj * TP + 4 * i4;
-      float4 x;
-      x.x = acc[(e0 + 0) / 16][(e0 + 0) % 16];
-      x.y = acc[(e0 + 1) / 16][(e0 + 1) % 16];
-      x.z = acc[(e0 + 2) / 16][(e0 + 2) % 16];
-      x.w = acc[(e0 + 3) / 16][(e0 + 3) % 16];
-      if (nvalid < ST) {
-        const int p = 4 * i4;
-        x.x = p + 0 < lim ? x.x : -INFINITY;
-        x.y = p + 1 < lim ? x.y : -INFINITY;
-        x.z = p + 2 < lim ? x.z : -INFINITY;
-        x.w = p + 3 < lim ? x.w : -INFINITY;
-      }
-      reinterpret_cast<float4*>(slot + pos0)[i4] = x;
-    }
-    __builtin_amdgcn_wave_barrier();
     float v[TP + kDetLook];
 #pragma unroll
-    for (int i4 = 0; i4 < (TP + kDetLook) / 4; ++i4) {
-      const float4 x = reinterpret_cast<const float4*>(slot + pos0)[i4];
-      v[4 * i4 + 0] = x.x;
-      v[4 * i4 + 1] = x.y;
-      v[4 * i4 + 2] = x.z;
-      v[4 * i4 + 3] = x.w;
-    }
+    for (int i = 0; i < TP; ++i) v[i] = acc[(jj * TP + i) / 16][(jj * TP + i) % 16];
     float bval[kDetNW];
     int bidx[kDetNW];
     double s1, s2;
-    if (nvalid < ST)
+    if (nvalid < ST) {
+#pragma unroll
+      for (int i = 0; i < TP; ++i) v[i] = i < lim ? v[i] : -INFINITY;
       det_lane_f32<TP, true>(v, owned, lim, bval, bidx, s1, s2);
-    else
+    } else {
       det_lane_f32<TP, false>(v, owned, lim, bval, bidx, s1, s2);
+    }
     det_commit_f32(a.det + ((int64_t)beam * a.rows_out + r) * a.n_time_tiles + tt, bval, bidx, s1, s2, pos0, t0);
-    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -400,23 +372,15 @@ __device__ __forceinline__ void win_tile(const TileArgs& a, int tt, int rt, int 
   }
 
   if constexpr (DET)
-    det_store_f32<TP, DPW, NWAVE>(a, acc, tt, rt, beam, t0, lds4);
+    det_store_f32<TP, DPW, NWAVE>(a, acc, tt, rt, beam, t0);
   else
     win_store<TP, DPW, NWAVE, ADJ>(a, acc, tt, rt, beam);
-}
-
-// LDS of a window kernel: the staged rows, or the search's per-wave series
-// if those need more.
-template <int TP, int NWAVE, int CC, int ROWCAP, int NBUF, bool DET>
-constexpr int win_lds_f4() {
-  return (DET && NWAVE * (64 * TP + kDetLook) > NBUF * CC * ROWCAP) ? NWAVE * (64 * TP + kDetLook) / 4
-                                                                      : NBUF * CC * ROWCAP / 4;
 }
 
 template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool WEIGHTED, bool ADJ,
           bool DET = false>
 __global__ __launch_bounds__(64 * NWAVE) void win_kernel(TileArgs a) {
-  __shared__ float4 lds4[win_lds_f4<TP, NWAVE, CC, ROWCAP, NBUF, DET>()];
+  __shared__ float4 lds4[NBUF * CC * ROWCAP / 4];
   const int nblk = a.n_time_tiles * a.n_row_tiles;
   const int W = xcd_remap(blockIdx.x, nblk);
   win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, WEIGHTED, ADJ, DET>(a, W / a.n_row_tiles, W % a.n_row_tiles,
@@ -747,8 +711,8 @@ __global__ __launch_bounds__(64 * NWAVE) void u8_kernel(TileArgs a) {
 // accept at most 256 input rows.  Sums are exact integers, so the order does
 // not matter.
 // ---------------------------------------------------------------------------
-template <int Q, int DPW, int NWAVE, int CC, int ROWCAP, bool WIDE, bool DET = false>
-__global__ __launch_bounds__(64 * NWAVE) void u8s_kernel(TileArgs a) {
+template <int Q, int DPW, int NWAVE, int CC, int ROWCAP, bool WIDE, bool DET>
+__device__ __forceinline__ void u8s_tile(const TileArgs& a) {
   constexpr int ST = 256 * Q;
   constexpr int DT = NWAVE * DPW;
   constexpr int WI = DPW <= 4 ? 4 : 8;  // ints per table entry
@@ -756,7 +720,7 @@ __global__ __launch_bounds__(64 * NWAVE) void u8s_kernel(TileArgs a) {
   static_assert(256 % CC == 0, "a flush every 256 rows must fall on a pass boundary");
   typedef typename std::conditional<(WI == 4), ent4_t, ent8_t>::type E;
   constexpr int LDS_STAGE = 4 * CC * ROWCAP / 16;
-  constexpr int LDS_DET = DET ? NWAVE * (ST + kDetLook) / 4 : 0;
+  constexpr int LDS_DET = DET ? NWAVE * ST / 4 : 0;
   __shared__ uint4 lds[LDS_STAGE > LDS_DET ? LDS_STAGE : LDS_DET];
   const int nblk = a.n_time_tiles * a.n_row_tiles;
   const int W = xcd_remap(blockIdx.x, nblk);
@@ -852,14 +816,15 @@ __global__ __launch_bounds__(64 * NWAVE) void u8s_kernel(TileArgs a) {
   if constexpr (DET) {
     // Single-pulse search in place of the store (see detect_dev.h): each
     // wave passes its rows one at a time through its own LDS slot, scaled by
-    // 2^IB for the keys, so every lane reads its L starts and the kDetLook
-    // samples after them.
+    // 2^IB for the keys, to give every lane L consecutive samples (the
+    // 16-byte chunks are XOR-swizzled within groups of eight so that both
+    // the writes and the reads are free of bank conflicts); the look-ahead
+    // comes from the lanes above.
     constexpr int L = 4 * Q;
     constexpr int IB = Q == 2 ? 3 : Q == 4 ? 4 : 5;
     static_assert((1 << IB) == L, "a lane's run is a power of two");
     __syncthreads();  // every wave is done with the staged rows
-    int* slot = reinterpret_cast<int*>(lds) + wave * (ST + kDetLook);
-    if (lane < kDetLook / 4) reinterpret_cast<int4*>(slot + ST)[lane] = make_int4(0, 0, 0, 0);
+    int4* slot = reinterpret_cast<int4*>(lds) + wave * (ST / 4);
     const int nvalid = min(ST, a.det_nsamp - t0);
     const int pos0 = L * lane;
     const bool owned = pos0 < a.tile_step;
@@ -868,6 +833,7 @@ __global__ __launch_bounds__(64 * NWAVE) void u8s_kernel(TileArgs a) {
     for (int jj = 0; jj < DPW; ++jj) {
       const int r = rt * DT + wave * DPW + jj;
       if (r >= a.rows_out) break;
+      __builtin_amdgcn_sched_barrier(0);  // one row at a time: keeps the search's registers to one row's
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         int s4[4];
@@ -877,17 +843,19 @@ __global__ __launch_bounds__(64 * NWAVE) void u8s_kernel(TileArgs a) {
         } else {
           unpack(jj, q, s4);
         }
-        reinterpret_cast<int4*>(slot)[lane + 64 * q] = make_int4(s4[0] << IB, s4[1] << IB, s4[2] << IB, s4[3] << IB);
+        const int m = lane + 64 * q;  // chunk of samples 4m .. 4m + 3
+        slot[m ^ ((m >> 2) & 7)] = make_int4(s4[0] << IB, s4[1] << IB, s4[2] << IB, s4[3] << IB);
       }
       __builtin_amdgcn_wave_barrier();
-      int v[L + kDetLook];
+      int v[L];
 #pragma unroll
-      for (int i4 = 0; i4 < (L + kDetLook) / 4; ++i4) {
-        const int4 x = reinterpret_cast<const int4*>(slot + pos0)[i4];
-        v[4 * i4 + 0] = x.x;
-        v[4 * i4 + 1] = x.y;
-        v[4 * i4 + 2] = x.z;
-        v[4 * i4 + 3] = x.w;
+      for (int c = 0; c < L / 4; ++c) {
+        const int m = (L / 4) * lane + c;
+        const int4 x = slot[m ^ ((m >> 2) & 7)];
+        v[4 * c + 0] = x.x;
+        v[4 * c + 1] = x.y;
+        v[4 * c + 2] = x.z;
+        v[4 * c + 3] = x.w;
       }
       int key[kDetNW];
       double s1, s2;
@@ -929,6 +897,17 @@ __global__ __launch_bounds__(64 * NWAVE) void u8s_kernel(TileArgs a) {
       }
     }
   }
+}
+
+template <int Q, int DPW, int NWAVE, int CC, int ROWCAP, bool WIDE>
+__global__ __launch_bounds__(64 * NWAVE) void u8s_kernel(TileArgs a) {
+  u8s_tile<Q, DPW, NWAVE, CC, ROWCAP, WIDE, false>(a);
+}
+
+// With the single-pulse search in the epilogue.
+template <int Q, int DPW, int NWAVE, int CC, int ROWCAP, bool WIDE>
+__global__ __launch_bounds__(64 * NWAVE) void u8s_det_kernel(TileArgs a) {
+  u8s_tile<Q, DPW, NWAVE, CC, ROWCAP, WIDE, true>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -1182,7 +1161,7 @@ hipError_t launch_detect(const Variant& v, const TileArgs& a, int nbeam, hipStre
   } else {
 #define LAUNCH_DU8(ID, Q, DPW, NW, CC, RC, WIDE)                                          \
   if (v.id == ID) {                                                                       \
-    hipLaunchKernelGGL((u8s_kernel<Q, DPW, NW, CC, RC, WIDE, true>), grid, block, 0, s, a); \
+    hipLaunchKernelGGL((u8s_det_kernel<Q, DPW, NW, CC, RC, WIDE>), grid, block, 0, s, a);   \
     return hipGetLastError();                                                             \
   }
     U8S_VARIANTS(LAUNCH_DU8)
