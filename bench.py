@@ -336,34 +336,26 @@ def main():
         # widths 1..32), the unfused path (store, then search) timed beside it
         p, b, x, o = plans[0], beams[0], xs[0], outs[0]
         dt = "u8" if b.dtype == "u8" else "f32"
-        ws = torch.empty(max(1, dd.lib().dedisp_detect_workspace_bytes(p.handle, dd._dt(dt), 1, b.nsamp) * 2),
-                         dtype=torch.uint8, device=dev)
+        # room for the unfused path too (the dedispersed rows and their records)
+        ws = torch.empty(b.ndm * (b.nsamp + 4) * 4 + (1 << 26), dtype=torch.uint8, device=dev)
         if args.variant is not None:
             p.set_variant(args.variant, dt)
+            p.set_detect_variant(args.variant, dt)
         elif not args.no_tune:
-            # forward variant for the unfused path, then the fastest fused variant
+            # the forward variant (used by the unfused path), then the search
+            # path: every fused variant and the unfused one, the fastest kept
             p.autotune(1, b.nsamp, dt)
             fwd = p.variant(dt)
-            cand = {}
-            for i in range(len(dd.variant_names(dt))):
-                try:
-                    p.set_variant(i, dt)
-                except dd.DedispError:
-                    continue
-                if p.detect_variant(dt) != i:
-                    continue
-                t_ms, _, _ = time_steps(lambda: dd.detect(x, p, nsamp=b.nsamp, workspace=ws), 3, 1, sync)
-                cand[i] = t_ms
-            extra["detect_tune_ms"] = {dd.variant_names(dt)[i]: round(v, 4) for i, v in cand.items()}
-            log(f"fused variants: {extra['detect_tune_ms']}")
-            p.set_variant(fwd, dt)
-            ms_u, _, _ = time_steps(lambda: (dd.dedisperse(x, p, nsamp=b.nsamp, out=o), dd.detect_rows(o)),
-                                    args.steps, args.warmup, sync)
+            extra["detect_tune_ms"] = {k: round(v, 4) for k, v in p.autotune_detect(1, b.nsamp, dt).items()}
+            log(f"search paths: {extra['detect_tune_ms']}")
+            chosen = p.detect_variant(dt)
+            p.set_detect_variant(-1, dt)
+            ms_u, _, _ = time_steps(lambda: dd.detect(x, p, nsamp=b.nsamp, workspace=ws), args.steps, args.warmup,
+                                    sync)
+            p.set_detect_variant(chosen, dt)
             extra["unfused_ms_per_step"] = ms_u
             extra["unfused_forward_variant"] = dd.variant_names(dt)[fwd] if fwd >= 0 else "direct"
             log(f"unfused (store, then search): {ms_u:.3f} ms/step")
-            if cand:
-                p.set_variant(min(cand, key=cand.get), dt)
         vi = p.detect_variant(dt)
         variant_name = dd.variant_names(dt)[vi] if vi >= 0 else "unfused"
         # algorithmic bytes: input once, delay table, the per-tile records and the results (no series)

@@ -238,6 +238,21 @@ size_t dedisp_detect_workspace_bytes(dedisp_plan plan, dedisp_dtype in_type, int
  * dedisp_variant_name(in_type, .)), or -1 for the unfused path. */
 int32_t dedisp_detect_variant(dedisp_plan plan, dedisp_dtype in_type);
 
+/* Force the search path for in_type: a variant with the search in its
+ * epilogue, -1 for the unfused path (dedisp_execute, then the row search),
+ * or -2 to go back to the automatic choice.  DEDISP_E_UNTUNED if the variant
+ * has no search epilogue or does not fit the plan; may build tile tables. */
+dedisp_status dedisp_plan_set_detect_variant(dedisp_plan plan, dedisp_dtype in_type, int32_t variant);
+
+/* Time every fused variant that fits and the unfused path (which uses the
+ * plan's current forward variant: tune that first) on nbeam x nsamp
+ * scratch samples of in_type, and keep the fastest for dedisp_detect.
+ * ms (may be NULL) receives up to n times: ms[i] for variant i (-1 if it
+ * does not fit), ms[dedisp_variant_count(in_type)] for the unfused path.
+ * Synchronous; allocates scratch memory. */
+dedisp_status dedisp_detect_autotune(dedisp_plan plan, int32_t nbeam, int32_t nsamp, dedisp_dtype in_type,
+                                     int32_t nwidth, float* ms, int32_t n);
+
 /* The same search over nrows stored series d_rows[nrows][stride] (F32, or
  * I32 searched in float32: exact while every boxcar sum is below 2^24 in
  * magnitude), with a workspace of dedisp_detect_rows_workspace_bytes(nrows,

@@ -158,6 +158,22 @@ class Plan:
         uses for dtype (-1: the unfused path)."""
         return int(lib().dedisp_detect_variant(self.handle, _dt(dtype)))
 
+    def set_detect_variant(self, index: int, dtype="f32"):
+        """Force the search path: a fused variant, -1 unfused, -2 automatic."""
+        check(lib().dedisp_plan_set_detect_variant(self.handle, _dt(dtype), index), "set_detect_variant")
+
+    def autotune_detect(self, nbeam: int, nsamp: int, dtype="f32", nwidth: int = 6) -> dict:
+        """Time the fused variants and the unfused path of the single-pulse
+        search, keep the fastest; returns {variant name or "unfused": ms}."""
+        names = variant_names(dtype)
+        ms = (ctypes.c_float * (len(names) + 1))()
+        check(lib().dedisp_detect_autotune(self.handle, nbeam, nsamp, _dt(dtype), nwidth, ms, len(names) + 1),
+              "detect_autotune")
+        out = {n: float(ms[i]) for i, n in enumerate(names) if ms[i] > 0}
+        if ms[len(names)] > 0:
+            out["unfused"] = float(ms[len(names)])
+        return out
+
     def autotune(self, nbeam: int, nsamp: int, dtype="f32", cache_path: str | None = None) -> dict:
         """Exhaustive search over the compiled variants; returns {name: ms}."""
         L = lib()

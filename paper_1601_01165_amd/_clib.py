@@ -46,6 +46,8 @@ SIGNATURES = {
     "dedisp_detect": (i32, [vp, i32, i32, vp, i32, i64, vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]),
     "dedisp_detect_workspace_bytes": (sz, [vp, i32, i32, i32]),
     "dedisp_detect_variant": (i32, [vp, i32]),
+    "dedisp_plan_set_detect_variant": (i32, [vp, i32, i32]),
+    "dedisp_detect_autotune": (i32, [vp, i32, i32, i32, i32, vp, i32]),
     "dedisp_detect_rows": (i32, [i32, i32, vp, i32, i64, i32, vp, vp, vp, vp, vp, vp, sz, vp]),
     "dedisp_detect_rows_workspace_bytes": (sz, [i32, i32]),
     "dedisp_status_string": (cp, [i32]),

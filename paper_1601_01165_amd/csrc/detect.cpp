@@ -18,18 +18,23 @@ static bool u8_sums_fit(const Variant& v, int nchan) {
   return (double)(run + kDetLook - 1) * 255.0 * nchan * scale < (double)(1 << 30);
 }
 
-// The variant of the fused search for this plan and dtype: the plan's forward
-// variant when it has a search epilogue and fits, else the first that fits
-// from a preference list, else -1 (unfused path).
-static int det_variant(dedisp_plan p, bool u8) {
+static bool det_fits(dedisp_plan p, bool u8, int vi) {
   const std::vector<Variant>& vs = u8 ? variants_u8() : variants_f32();
-  auto fits = [&](int vi) {
-    if (vi < 0 || vi >= (int)vs.size()) return false;
-    const Variant& v = vs[vi];
-    if (!detect_fusable(v)) return false;
-    if (u8 && !u8_sums_fit(v, p->nchan)) return false;
-    return ensure_tables(p, u8 ? 1 : 0, vi, nullptr) == DEDISP_OK;
-  };
+  if (vi < 0 || vi >= (int)vs.size()) return false;
+  const Variant& v = vs[vi];
+  if (!detect_fusable(v)) return false;
+  if (u8 && !u8_sums_fit(v, p->nchan)) return false;
+  return ensure_tables(p, u8 ? 1 : 0, vi, nullptr) == DEDISP_OK;
+}
+
+// The variant of the search for this plan and dtype: the one set or tuned
+// (-1: unfused); otherwise the plan's forward variant when it has a search
+// epilogue and fits, else the first that fits from a preference list, else
+// -1.
+static int det_variant(dedisp_plan p, bool u8) {
+  const int set = u8 ? p->var_det_u8 : p->var_det_f32;
+  if (set >= -1) return set;
+  auto fits = [&](int vi) { return det_fits(p, u8, vi); };
   const int cur = u8 ? p->var_u8 : p->var_f32;
   if (fits(cur)) return cur;
   static const int pref_f32[] = {15, 13, 17, 16, 14, 18};
@@ -113,7 +118,9 @@ dedisp_status dedisp_detect(dedisp_plan p, int32_t nbeam, int32_t nsamp, const v
   const int vi = det_variant(p, u8);
   hipError_t e;
   if (vi < 0) {
-    // no variant with the search in its epilogue fits: dedisperse into the workspace, then search the rows
+    // unfused (no variant with the search in its epilogue fits, or the
+    // unfused path was set or tuned): dedisperse into the workspace, then
+    // search the stored rows
     const int64_t stride = round_up(nsamp, 4);
     void* rows = d_ws;
     DetRec* recs = (DetRec*)((char*)d_ws + round_up((size_t)nseries * stride * 4, 256));
@@ -151,12 +158,97 @@ dedisp_status dedisp_detect(dedisp_plan p, int32_t nbeam, int32_t nsamp, const v
   a.out = nullptr;
   a.tile_step = step;
   a.det_nsamp = nsamp;
+  // a lane's sum of squares in 32 bits: run * (255 * nchan)^2 < 2^32
+  a.det_s2_u32 = u8 && (double)(4 * v.tp) * (255.0 * p->nchan) * (255.0 * p->nchan) < 4294967296.0;
   a.det = (DetRec*)d_ws;
   e = launch_detect(v, a, nbeam, s);
   if (e != hipSuccess) return hip_fail(e, "launching the fused search");
   e = launch_det_finish(a.det, u8, (int)nseries, a.n_time_tiles, nsamp, nwidth, d_snr, d_width, d_start, d_mean,
                         d_std, s);
   return e == hipSuccess ? DEDISP_OK : hip_fail(e, "launching the record merge");
+}
+
+dedisp_status dedisp_plan_set_detect_variant(dedisp_plan p, dedisp_dtype in_type, int32_t vi) {
+  if (!p) return fail(DEDISP_E_INVALID, "plan is NULL");
+  if (in_type != DEDISP_F32 && in_type != DEDISP_U8) return fail(DEDISP_E_DTYPE, "dtype must be F32 or U8");
+  const bool u8 = in_type == DEDISP_U8;
+  const int n = (int)(u8 ? variants_u8() : variants_f32()).size();
+  if (vi < -2 || vi >= n) return fail(DEDISP_E_INVALID, "variant index out of range");
+  if (vi >= 0 && !det_fits(p, u8, vi)) return fail(DEDISP_E_UNTUNED, "variant has no search epilogue or does not fit");
+  (u8 ? p->var_det_u8 : p->var_det_f32) = vi;
+  return DEDISP_OK;
+}
+
+dedisp_status dedisp_detect_autotune(dedisp_plan p, int32_t nbeam, int32_t nsamp, dedisp_dtype in_type, int32_t nwidth,
+                                     float* ms, int32_t n) {
+  if (!p) return fail(DEDISP_E_INVALID, "plan is NULL");
+  if (nbeam < 1 || nsamp < 1) return fail(DEDISP_E_INVALID, "nbeam and nsamp must be >= 1");
+  if (in_type != DEDISP_F32 && in_type != DEDISP_U8) return fail(DEDISP_E_DTYPE, "dtype must be F32 or U8");
+  if (nwidth < 1 || nwidth > kDetNW) return fail(DEDISP_E_INVALID, "nwidth must be in [1, 6]");
+  const bool u8 = in_type == DEDISP_U8;
+  const int nv = (int)(u8 ? variants_u8() : variants_f32()).size();
+  const int esz = u8 ? 1 : 4;
+  const int64_t q = 16 / esz;
+  const int64_t in_stride = ((int64_t)nsamp + p->max_delay + q - 1) / q * q;
+  const int64_t nseries = (int64_t)nbeam * p->ndm;
+  // the unfused path needs the most workspace
+  const size_t ws_bytes = fallback_ws(p, nbeam, nsamp);
+  void *d_in = nullptr, *d_ws = nullptr, *d_res = nullptr;
+  hipError_t e = hipMalloc(&d_in, (size_t)nbeam * p->nchan * in_stride * esz);
+  if (e == hipSuccess) e = hipMalloc(&d_ws, ws_bytes);
+  if (e == hipSuccess) e = hipMalloc(&d_res, (size_t)nseries * 16);
+  if (e == hipSuccess) e = launch_fill_random(d_in, (size_t)nbeam * p->nchan * in_stride * esz, !u8, 1601u, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    if (d_in) (void)hipFree(d_in);
+    if (d_ws) (void)hipFree(d_ws);
+    return e == hipErrorOutOfMemory ? fail(DEDISP_E_NOMEM, "autotune scratch allocation failed")
+                                    : hip_fail(e, "autotune scratch");
+  }
+  double* snr = (double*)d_res;
+  int32_t* wid = (int32_t*)(snr + nseries);
+  int32_t* start = wid + nseries;
+  hipStream_t s;
+  hipEvent_t e0, e1;
+  (void)hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  int& var = u8 ? p->var_det_u8 : p->var_det_f32;
+  const int saved = var;
+  std::vector<float> times(nv + 1, -1.f);
+  int best = -2;
+  float best_ms = 1e30f;
+  for (int vi = -1; vi < nv; ++vi) {
+    if (vi >= 0 && !det_fits(p, u8, vi)) continue;
+    var = vi;
+    const float t = median_ms(
+        [&]() {
+          return dedisp_detect(p, nbeam, nsamp, d_in, in_type, in_stride, nullptr, nwidth, snr, wid, start, nullptr,
+                               nullptr, d_ws, ws_bytes, s) == DEDISP_OK
+                     ? hipSuccess
+                     : hipErrorUnknown;
+        },
+        s, 3, e0, e1);
+    times[vi < 0 ? nv : vi] = t;
+    if (t > 0 && t < best_ms) {
+      best_ms = t;
+      best = vi;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  (void)hipFree(d_in);
+  (void)hipFree(d_ws);
+  (void)hipFree(d_res);
+  if (ms)
+    for (int i = 0; i < n && i <= nv; ++i) ms[i] = times[i];
+  if (best == -2) {
+    var = saved;
+    return fail(DEDISP_E_UNTUNED, "no search path ran");
+  }
+  var = best;
+  return DEDISP_OK;
 }
 
 size_t dedisp_detect_rows_workspace_bytes(int32_t nrows, int32_t nsamp) {

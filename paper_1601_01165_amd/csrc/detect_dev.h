@@ -195,16 +195,28 @@ __device__ __forceinline__ void det_commit_f32(DetRec* rec, const float* bval, c
 // look-ahead step reads stay live.  Per width the lane's largest key
 // (negative: none).
 template <int L, int IB, bool MASK>
-__device__ __forceinline__ void det_lane_int(const int* v, bool owned, int lim, int* key, double& s1, double& s2) {
+__device__ __forceinline__ void det_lane_int(const int* v, bool owned, int lim, bool s2_u32, int* key, double& s1,
+                                             double& s2) {
   int s1i = 0;
-  s2 = 0.0;
+  if (s2_u32) {
+    // every y < 2^24 and the lane's sum of squares < 2^32 (the host checks)
+    uint32_t q = 0;
 #pragma unroll
-  for (int i = 0; i < L; ++i) {
-    const int y = v[i] >> IB;
-    const bool ok = !MASK || i < lim;
-    s1i += ok ? y : 0;
-    const double yd = (double)(ok ? y : 0);
-    s2 = fma(yd, yd, s2);
+    for (int i = 0; i < L; ++i) {
+      const uint32_t y = (!MASK || i < lim) ? (uint32_t)(v[i] >> IB) : 0u;
+      s1i += (int)y;
+      q += __umul24(y, y);
+    }
+    s2 = (double)q;
+  } else {
+    s2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      const int y = (!MASK || i < lim) ? v[i] >> IB : 0;
+      s1i += y;
+      const double yd = (double)y;
+      s2 = fma(yd, yd, s2);
+    }
   }
   s1 = owned ? (double)s1i : 0.0;
   if (!owned) s2 = 0.0;

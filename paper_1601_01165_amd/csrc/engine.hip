@@ -860,9 +860,9 @@ __device__ __forceinline__ void u8s_tile(const TileArgs& a) {
       int key[kDetNW];
       double s1, s2;
       if (nvalid < ST)
-        det_lane_int<L, IB, true>(v, owned, lim, key, s1, s2);
+        det_lane_int<L, IB, true>(v, owned, lim, a.det_s2_u32 != 0, key, s1, s2);
       else
-        det_lane_int<L, IB, false>(v, owned, lim, key, s1, s2);
+        det_lane_int<L, IB, false>(v, owned, lim, a.det_s2_u32 != 0, key, s1, s2);
       det_commit_int<L, IB>(a.det + ((int64_t)beam * a.rows_out + r) * a.n_time_tiles + tt, key, s1, s2, pos0, t0);
       __builtin_amdgcn_wave_barrier();
     }

@@ -113,6 +113,7 @@ struct TileArgs {
   // single-pulse search launches only
   int tile_step;             // samples between time tiles = window starts owned by a tile
   int det_nsamp;             // samples of each dedispersed series
+  int det_s2_u32;            // uint8: a lane's sum of squares fits 32 bits
   DetRec* det;               // [beam][rows_out][n_time_tiles]
 };
 
@@ -188,4 +189,5 @@ struct dedisp_plan_s {
   int adj_pad = 0;                  // max_delay rounded up to a multiple of 4
   std::map<int, dd::Tables> fwd_f32, fwd_u8, adj_f32;
   int var_f32 = -2, var_u8 = -2, var_adj = -2;  // -1 = direct kernel, -2 = not chosen yet
+  int var_det_f32 = -2, var_det_u8 = -2;         // single-pulse search: -1 = unfused, -2 = automatic
 };

@@ -356,3 +356,33 @@ def test_detect_errors():
                          ctypes.c_void_p(o.data_ptr()), ctypes.c_void_p(wi.data_ptr()),
                          ctypes.c_void_p(wi.data_ptr()), None, None, ctypes.c_void_p(o.data_ptr()), 8, None)
     assert st == 8  # workspace too small
+
+
+def test_detect_autotune_and_forced_paths():
+    # the tuner times every fused variant and the unfused path and keeps one;
+    # every path gives the same uint8 result
+    dd = _dd()
+    b = synth.config(2)[0]
+    dms = b.dms()[:64]
+    plan = dd.Plan(b.freqs(), b.tsamp_s, dms)
+    ns = 6000
+    x = synth.noise(b, ns + plan.max_delay)[None]
+    xg = _to_gpu(x)
+    times = plan.autotune_detect(1, ns, "u8")
+    _note(f"detect autotune: {times}")
+    assert "unfused" in times and len(times) >= 9
+    best = min(times, key=times.get)
+    chosen = plan.detect_variant("u8")
+    assert (best == "unfused" and chosen == -1) or dd.variant_names("u8")[chosen] == best
+    ref = _cpu(dd.detect(xg, plan, nsamp=ns))
+    _check_exact(ref, oracle.forward_u8(x, oracle.delay_table(b.freqs(), b.tsamp_s, dms), ns), 6, "tuned")
+    for v in (-1, 12, 16, 20):
+        plan.set_detect_variant(v, "u8")
+        assert plan.detect_variant("u8") == v
+        got = _cpu(dd.detect(xg, plan, nsamp=ns))
+        for k in ref:
+            assert np.array_equal(got[k], ref[k]), (v, k)
+    with pytest.raises(dd.DedispError):
+        plan.set_detect_variant(0, "u8")  # one-copy variant: no search epilogue
+    plan.set_detect_variant(-2, "u8")
+    assert plan.detect_variant("u8") >= 0
