@@ -195,7 +195,7 @@ def kernel_sources_hash():
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("engine.hip", "win_asm.inc"):
+    for f in ("engine.hip", "win_asm.inc", "detect_dev.h"):
         with open(os.path.join(ROOT, "paper_1601_01165_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

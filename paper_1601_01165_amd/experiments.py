@@ -20,6 +20,10 @@ Prints one JSON object per experiment:
   time (the paper: 9 per HD7970).
 * ``streaming``: the same as a stream of consecutive 1 s chunks with a
   max-delay halo, each chunk one graph replay, checked against one long run.
+* ``detect``: dedispersion followed by the single-pulse search (boxcar S/N,
+  widths 1..32) on the Apertif-like (2,000 DMs) and LOFAR-like (2,048 DMs)
+  set-ups: the tuned search path against the unfused one, and the beams one
+  GPU dedisperses and searches in real time.
 
 All inputs are synthetic (seeded noise); only timings are reported.
 """
@@ -33,7 +37,7 @@ import time
 import numpy as np
 import torch
 
-from . import Batch, Plan, dedisperse, empty_rows
+from . import Batch, Plan, dedisperse, detect, empty_rows
 
 
 def _setup(name):
@@ -155,6 +159,25 @@ def streaming(nbeams=16, nchunks=4, nd=2000):
             "ms": ms, "chunked_equals_whole": ok, "beams_realtime": seconds_of_data / (ms * 1e-3)}
 
 
+def detect_realtime(name, nd):
+    f, ts, ns, step, dtype = _setup(name)
+    dt = "u8" if dtype == torch.uint8 else "f32"
+    p = Plan(f, ts, np.arange(nd) * step)
+    x = _input(len(f), ns + p.max_delay, dtype, 11)
+    p.autotune(1, ns, dt)
+    paths = p.autotune_detect(1, ns, dt)
+    chosen = p.detect_variant(dt)
+    ws = torch.empty(nd * (ns + 4) * 4 + (1 << 26), dtype=torch.uint8, device="cuda")
+    tuned = _time(lambda: detect(x, p, nsamp=ns, workspace=ws))
+    p.set_detect_variant(-1, dt)
+    unfused = _time(lambda: detect(x, p, nsamp=ns, workspace=ws))
+    fused = {k: v for k, v in paths.items() if k != "unfused"}
+    return {"setup": name, "ndm": nd, "samples": ns, "tuned_ms": tuned, "unfused_ms": unfused,
+            "best_fused_ms": min(fused.values()) if fused else None,
+            "chosen": "unfused" if chosen < 0 else min(fused, key=fused.get),
+            "beams_realtime": ns * ts / (tuned * 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true")
@@ -169,6 +192,8 @@ def main():
     print(json.dumps({"experiment": "histogram", "setup": "apertif", "ndm": 2048, "ms": histogram()}), flush=True)
     print(json.dumps({"experiment": "realtime_beams", **realtime_beams(16 if args.quick else 64)}), flush=True)
     print(json.dumps({"experiment": "streaming", **streaming(8 if args.quick else 16)}), flush=True)
+    for name, nd in (("apertif", 2000), ("lofar", 2048)):
+        print(json.dumps({"experiment": "detect", **detect_realtime(name, nd)}), flush=True)
     print(f"experiments done in {time.time() - t0:.1f} s", file=sys.stderr)
 
 
