@@ -202,6 +202,7 @@ dedisp_status dedisp_detect_autotune(dedisp_plan p, int32_t nbeam, int32_t nsamp
   if (e != hipSuccess) {
     if (d_in) (void)hipFree(d_in);
     if (d_ws) (void)hipFree(d_ws);
+    if (d_res) (void)hipFree(d_res);
     return e == hipErrorOutOfMemory ? fail(DEDISP_E_NOMEM, "autotune scratch allocation failed")
                                     : hip_fail(e, "autotune scratch");
   }

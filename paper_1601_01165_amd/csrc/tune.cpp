@@ -154,6 +154,7 @@ dedisp_status dedisp_autotune(dedisp_plan p, int32_t nbeam, int32_t nsamp, dedis
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     if (d_in) (void)hipFree(d_in);
+    if (d_out) (void)hipFree(d_out);
     return e == hipErrorOutOfMemory ? fail(DEDISP_E_NOMEM, "autotune scratch allocation failed")
                                     : hip_fail(e, "autotune scratch");
   }
