@@ -171,3 +171,46 @@ def test_batched_every_variant(weighted):
         batch.set_variant(len(names))
     batch.execute()
     torch.cuda.synchronize()
+
+
+def test_config3_full_size_sampled():
+    """The batched workload at full size (256 uneven beams, 20.7 GB in, 33.9 GB
+    out) in the tuned persistent launch the benchmark times, checked against
+    the oracle on 4,000 sampled outputs of each of 10 beams (the beams with
+    the most channels and the most DM trials among them), bit for bit."""
+    dd = _dd()
+    beams = synth.config(3)
+    plans, xs, outs = [], [], []
+    for i, b in enumerate(beams):
+        p = dd.Plan(b.freqs(), b.tsamp_s, b.dms())
+        x = dd.empty_rows(1, b.nchan, b.nsamp + p.max_delay, torch.float32, "cuda")
+        g = torch.Generator(device="cuda")
+        g.manual_seed(b.seed)
+        x.copy_(torch.randn(x.shape, generator=g, device="cuda"))
+        plans.append(p)
+        xs.append(x)
+        outs.append(dd.empty_rows(1, b.ndm, b.nsamp, torch.float32, "cuda"))
+        if i % 64 == 63:
+            _note(f"config3: {i + 1} beams prepared")
+    batch = dd.Batch(plans, xs, outs, tune=True)
+    _note(f"config3: tuned variant {dd.variant_names('f32')[batch.variant]}")
+    for o in outs:
+        o.fill_(float("nan"))
+    batch.execute()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    pick = set(rng.choice(len(beams), 8, replace=False).tolist())
+    pick.add(max(range(len(beams)), key=lambda i: beams[i].nchan * beams[i].ndm))
+    pick.add(max(range(len(beams)), key=lambda i: beams[i].ndm))
+    for i in sorted(pick):
+        b = beams[i]
+        delta = oracle.delay_table(b.freqs(), b.tsamp_s, b.dms())
+        x = np.ascontiguousarray(xs[i].cpu().numpy())
+        pd = rng.integers(0, b.ndm, 4000)
+        ps = rng.integers(0, b.nsamp, 4000)
+        pd[:2] = [0, b.ndm - 1]
+        ps[:2] = [0, b.nsamp - 1]
+        ref, _ = oracle.forward_points(x, delta, np.zeros(4000, np.int32), pd, ps)
+        got = outs[i][0].cpu().numpy()[pd, ps]
+        _note(f"config3 beam {i}: {b.nchan} ch, {b.ndm} DMs, {b.nsamp} samples")
+        assert np.array_equal(got, ref), f"beam {i}"
