@@ -120,6 +120,41 @@ def test_adjoint_dot_identity_config4_geometry():
     assert lhs == rhs  # small integers: every sum is exact
 
 
+def test_adjoint_config4_full_size_sampled():
+    """The differentiable workload at full size (32 beams, 1024 channels, 1024
+    DMs, 20,000 samples) in the adjoint launch the benchmark times: grad_in
+    bit for bit on 6 channels of 2 beams, grad_w on those 6 channels (summed
+    over all 32 beams) within 1e-5 of sum |g * x|."""
+    dd = _dd()
+    beams = synth.config(4)
+    b = beams[0]
+    plan = dd.Plan(b.freqs(), b.tsamp_s, b.dms())
+    nin = b.nsamp + plan.max_delay
+    nb = len(beams)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(404)
+    x = _rows(np.zeros((nb, b.nchan, nin), np.float32))
+    x.copy_(torch.randn(x.shape, generator=gen, device="cuda"))
+    g = _rows(np.zeros((nb, b.ndm, b.nsamp), np.float32))
+    g.copy_(torch.randn(g.shape, generator=gen, device="cuda"))
+    w = torch.rand(b.nchan, generator=gen, device="cuda") + 0.5
+    _note(f"config4 full size: adjoint variant {plan.adjoint_variant()}")
+    gi, gw = dd.adjoint(g, plan, nin, w, x)
+    torch.cuda.synchronize()
+    delta = oracle.delay_table(b.freqs(), b.tsamp_s, b.dms())
+    chans = np.array([0, 1, 333, 511, 900, b.nchan - 1])
+    wn = w.cpu().numpy()
+    gn = np.ascontiguousarray(g.cpu().numpy())
+    for bi in (0, nb - 1):
+        ref = oracle.adjoint_gather_f32(gn[bi:bi + 1], np.ascontiguousarray(delta[:, chans]), nin, wn[chans])
+        got = gi[bi, chans].cpu().numpy()
+        assert np.array_equal(got, ref[0]), f"grad_in beam {bi}"
+    xs = np.ascontiguousarray(x[:, chans].cpu().numpy())
+    ref_gw, scale = oracle.grad_w(xs, gn, np.ascontiguousarray(delta[:, chans]))
+    got_gw = gw.cpu().numpy()[chans].astype(np.float64)
+    assert (np.abs(got_gw - ref_gw) <= 1e-5 * scale + 1e-6 * np.abs(ref_gw)).all()
+
+
 def _snr_t(y):
     return (y.max() - y.mean()) / y.std(correction=0)
 
