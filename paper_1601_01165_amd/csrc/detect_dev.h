@@ -30,49 +30,38 @@ namespace dd {
 // broadcasts (no LDS traffic): shifts by 1, 2, 4 and 8 lanes leave each
 // 16-lane row's result in its lane 15, broadcasting lane 15 into rows 1 and 3
 // and then lane 31 into rows 2 and 3 leaves the wave's result in lane 63,
-// which is read as a scalar.  Lanes whose DPP source is out of range or
-// masked take `old`: the value itself for max/min, zero for sums.  The
-// order of the additions is fixed, so sums are reproducible.
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ int det_dpp(int old, int x) {
-  return __builtin_amdgcn_update_dpp(old, x, CTRL, ROWMASK, 0xf, false);
-}
-
-#define DET_WAVE_REDUCE(OP, OLD)                   \
-  x = OP(x, det_dpp<0x111, 0xf>(OLD, x));          \
-  x = OP(x, det_dpp<0x112, 0xf>(OLD, x));          \
-  x = OP(x, det_dpp<0x114, 0xf>(OLD, x));          \
-  x = OP(x, det_dpp<0x118, 0xf>(OLD, x));          \
-  x = OP(x, det_dpp<0x142, 0xa>(OLD, x));          \
-  x = OP(x, det_dpp<0x143, 0xc>(OLD, x));
-
-__device__ __forceinline__ int det_imax(int a, int b) { return max(a, b); }
-__device__ __forceinline__ int det_imin(int a, int b) { return min(a, b); }
-__device__ __forceinline__ int det_iadd(int a, int b) { return a + b; }
+// which is read as a scalar.  Each step is one in-place DPP instruction: it
+// writes only the lanes whose source lane is in range and whose row is
+// enabled, the others keep their value.  A vector result read through DPP
+// needs two wait states, hence the s_nop before each step.
+#define DET_DPP_STEPS(OP)                                                   \
+  "s_nop 1\n\t" OP " %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"    \
+  "s_nop 1\n\t" OP " %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"    \
+  "s_nop 1\n\t" OP " %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"    \
+  "s_nop 1\n\t" OP " %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"    \
+  "s_nop 1\n\t" OP " %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t" \
+  "s_nop 1\n\t" OP " %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t" \
+  "s_nop 1"
 
 __device__ __forceinline__ int det_wave_max(int x) {
-  DET_WAVE_REDUCE(det_imax, x)
+  asm volatile(DET_DPP_STEPS("v_max_i32_dpp") : "+v"(x));
   return __builtin_amdgcn_readlane(x, 63);
 }
 
 __device__ __forceinline__ int det_wave_min(int x) {
-  DET_WAVE_REDUCE(det_imin, x)
+  asm volatile(DET_DPP_STEPS("v_min_i32_dpp") : "+v"(x));
   return __builtin_amdgcn_readlane(x, 63);
 }
 
-__device__ __forceinline__ int det_wave_sum_i(int x) {
-  DET_WAVE_REDUCE(det_iadd, 0)
-  return __builtin_amdgcn_readlane(x, 63);
+__device__ __forceinline__ float det_wave_maxf(float x) {
+  asm volatile(DET_DPP_STEPS("v_max_f32_dpp") : "+v"(x));
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
-__device__ __forceinline__ int det_fmax_bits(int a, int b) {
-  return __float_as_int(fmaxf(__int_as_float(a), __int_as_float(b)));
-}
-
-__device__ __forceinline__ float det_wave_maxf(float xf) {
-  int x = __float_as_int(xf);
-  DET_WAVE_REDUCE(det_fmax_bits, x)
-  return __int_as_float(__builtin_amdgcn_readlane(x, 63));
+// Lanes whose DPP source is out of range or whose row is masked take `old`.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int det_dpp(int old, int x) {
+  return __builtin_amdgcn_update_dpp(old, x, CTRL, ROWMASK, 0xf, false);
 }
 
 template <int CTRL, int ROWMASK>
@@ -187,10 +176,10 @@ __device__ __forceinline__ void det_commit_f32(DetRec* rec, const float* bval, c
 // next lane's E(j - L)), the key
 //   E(i + w) - (E(i) - (L - 1 - i)) = (B_w(i) << IB) + (L - 1 - i)
 // orders windows by sum and, for equal sums, the earlier start first, so one
-// integer max per window finds both.  Starts outside the tile's owned range
-// or past the series end get E(i) := 2^30, entries past the end -2^30, which
-// makes every key that touches them negative (the host limits sums to keep
-// |E| < 2^30).  One pass in order of j: E(j) closes the window of width w
+// integer max per window finds both.  Starts past the series end get
+// E(i) := 2^30 and entries past the end -2^30, which makes every key that
+// touches them negative (the host limits sums to keep |E| < 2^30); lanes
+// whose starts lie outside the tile's owned range report no window.  One pass in order of j: E(j) closes the window of width w
 // that starts at j - w, so only the L start terms and the entries the next
 // look-ahead step reads stay live.  Per width the lane's largest key
 // (negative: none).
@@ -231,16 +220,16 @@ __device__ __forceinline__ void det_lane_int(const int* v, bool owned, int lim, 
       const int e = j <= L ? E[j - 1] + v[j - 1] : E[L] + det_next_lane(0, E[j - L]);
       E[j] = (MASK && j > lim) ? -(1 << 30) : e;
     }
-    if (j < L) {
-      const bool start_ok = owned && (!MASK || j < lim);
-      Q[j] = start_ok ? E[j] - (L - 1 - j) : (1 << 30);
-    }
+    if (j < L) Q[j] = (!MASK || j < lim) ? E[j] - (L - 1 - j) : (1 << 30);
 #pragma unroll
     for (int k = 0; k < kDetNW; ++k) {
       const int i = j - (1 << k);
       if (i >= 0 && i < L) key[k] = max(key[k], E[j] - Q[i]);
     }
   }
+  // starts outside the tile's owned range: no window
+#pragma unroll
+  for (int k = 0; k < kDetNW; ++k) key[k] = owned ? key[k] : INT32_MIN;
 }
 
 template <int L, int IB>
