@@ -377,12 +377,22 @@ def main():
         xs, outs = [xb], [ob]
         adds *= 2
         nin = xb.shape[2]
+        if args.variant is not None:
+            p0.set_variant(args.variant, "f32")
+            p0.set_adjoint_variant(args.variant)
+        elif not args.no_tune:
+            p0.autotune(len(beams), beams[0].nsamp, "f32")
+            times = p0.autotune_adjoint(len(beams), beams[0].nsamp)
+            extra["adjoint_tune_ms"] = {k: round(v, 3) for k, v in times.items()}
+            log(f"adjoint variants: {extra['adjoint_tune_ms']}")
 
         def step():
             dd.dedisperse(xb, p0, w, nsamp=beams[0].nsamp, out=ob)
             dd.adjoint(g, p0, nin, w, xb)
         kernel_name = "win_kernel (forward + adjoint)"
-        variant_name = f"{dd.variant_names('f32')[p0.variant('f32')]} (forward)"
+        fv, av = p0.variant("f32"), p0.adjoint_variant()
+        variant_name = (f"{dd.variant_names('f32')[fv] if fv >= 0 else 'direct'} (forward), "
+                        f"{dd.variant_names('f32')[av] if av >= 0 else 'direct'} (adjoint)")
 
     log("timing")
     ms, launch_ms, wall = time_steps(step, args.steps, args.warmup, sync)

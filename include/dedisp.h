@@ -303,6 +303,15 @@ int32_t dedisp_plan_variant(dedisp_plan plan, dedisp_dtype in_type);
 dedisp_status dedisp_plan_set_adjoint_variant(dedisp_plan plan, int32_t variant);
 int32_t dedisp_plan_adjoint_variant(dedisp_plan plan);
 
+/* Auto-tuning of the adjoint (an extension of the paper's tuning, §2.2):
+ * time every variant that fits, and the direct adjoint kernel, on nbeam
+ * beams of nsamp output samples of scratch data (grad_in and grad_w both
+ * computed, as in training), and keep the fastest for dedisp_adjoint.
+ * ms (may be NULL) receives up to n times: ms[i] for variant i (-1 if it
+ * did not fit), ms[dedisp_variant_count(DEDISP_F32)] for the direct kernel.
+ * Synchronous; allocates scratch memory. */
+dedisp_status dedisp_autotune_adjoint(dedisp_plan plan, int32_t nbeam, int32_t nsamp, float* ms, int32_t n);
+
 /* ------------------------------------------------------------------------ */
 /* Errors                                                                    */
 /* ------------------------------------------------------------------------ */

@@ -158,6 +158,17 @@ class Plan:
         uses for dtype (-1: the unfused path)."""
         return int(lib().dedisp_detect_variant(self.handle, _dt(dtype)))
 
+    def autotune_adjoint(self, nbeam: int, nsamp: int) -> dict:
+        """Time every adjoint variant and the direct adjoint, keep the
+        fastest; returns {variant name or "direct": ms}."""
+        names = variant_names("f32")
+        ms = (ctypes.c_float * (len(names) + 1))()
+        check(lib().dedisp_autotune_adjoint(self.handle, nbeam, nsamp, ms, len(names) + 1), "autotune_adjoint")
+        out = {n: float(ms[i]) for i, n in enumerate(names) if ms[i] > 0}
+        if ms[len(names)] > 0:
+            out["direct"] = float(ms[len(names)])
+        return out
+
     def set_detect_variant(self, index: int, dtype="f32"):
         """Force the search path: a fused variant, -1 unfused, -2 automatic."""
         check(lib().dedisp_plan_set_detect_variant(self.handle, _dt(dtype), index), "set_detect_variant")

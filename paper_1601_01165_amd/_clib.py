@@ -37,6 +37,7 @@ SIGNATURES = {
     "dedisp_batch_destroy": (i32, [vp]),
     "dedisp_autotune": (i32, [vp, i32, i32, i32, cp]),
     "dedisp_autotune_times": (i32, [vp, i32, vp, i32]),
+    "dedisp_autotune_adjoint": (i32, [vp, i32, i32, vp, i32]),
     "dedisp_variant_count": (i32, [i32]),
     "dedisp_variant_name": (cp, [i32, i32]),
     "dedisp_plan_set_variant": (i32, [vp, i32, i32]),

@@ -199,6 +199,70 @@ dedisp_status dedisp_autotune(dedisp_plan p, int32_t nbeam, int32_t nsamp, dedis
   return DEDISP_OK;
 }
 
+dedisp_status dedisp_autotune_adjoint(dedisp_plan p, int32_t nbeam, int32_t nsamp, float* ms, int32_t n) {
+  if (!p) return fail(DEDISP_E_INVALID, "plan is NULL");
+  if (nbeam < 1 || nsamp < 1) return fail(DEDISP_E_INVALID, "nbeam and nsamp must be >= 1");
+  const std::vector<Variant>& vs = variants_f32();
+  const int64_t nin = ((int64_t)nsamp + p->max_delay + 3) / 4 * 4;
+  const int64_t gs = ((int64_t)nsamp + 3) / 4 * 4;
+  const size_t ws_bytes = dedisp_adjoint_workspace_bytes(p, nbeam, (int32_t)nin);
+  float *d_g = nullptr, *d_x = nullptr, *d_gi = nullptr, *d_gw = nullptr;
+  void* d_ws = nullptr;
+  hipError_t e = hipMalloc(&d_g, (size_t)nbeam * p->ndm * gs * 4);
+  if (e == hipSuccess) e = hipMalloc(&d_x, (size_t)nbeam * p->nchan * nin * 4);
+  if (e == hipSuccess) e = hipMalloc(&d_gi, (size_t)nbeam * p->nchan * nin * 4);
+  if (e == hipSuccess) e = hipMalloc(&d_gw, (size_t)p->nchan * 4);
+  if (e == hipSuccess) e = hipMalloc(&d_ws, std::max<size_t>(ws_bytes, 16));
+  if (e == hipSuccess) e = launch_fill_random(d_g, (size_t)nbeam * p->ndm * gs * 4, true, 1602u, nullptr);
+  if (e == hipSuccess) e = launch_fill_random(d_x, (size_t)nbeam * p->nchan * nin * 4, true, 1603u, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  auto release = [&]() {
+    for (void* q : {(void*)d_g, (void*)d_x, (void*)d_gi, (void*)d_gw, d_ws})
+      if (q) (void)hipFree(q);
+  };
+  if (e != hipSuccess) {
+    release();
+    return e == hipErrorOutOfMemory ? fail(DEDISP_E_NOMEM, "autotune scratch allocation failed")
+                                    : hip_fail(e, "autotune scratch");
+  }
+  hipStream_t s;
+  hipEvent_t e0, e1;
+  (void)hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const int saved = p->var_adj;
+  std::vector<float> times(vs.size() + 1, -1.f);
+  int best = -2;
+  float best_ms = 1e30f;
+  for (int vi = -1; vi < (int)vs.size(); ++vi) {
+    if (dedisp_plan_set_adjoint_variant(p, vi) != DEDISP_OK) continue;
+    const float t = median_ms(
+        [&]() {
+          return dedisp_adjoint(p, nbeam, nsamp, (int32_t)nin, d_g, gs, nullptr, d_x, nin, d_gi, nin, d_gw, d_ws,
+                                ws_bytes, s) == DEDISP_OK
+                     ? hipSuccess
+                     : hipErrorUnknown;
+        },
+        s, 3, e0, e1);
+    times[vi < 0 ? vs.size() : (size_t)vi] = t;
+    if (t > 0 && t < best_ms) {
+      best_ms = t;
+      best = vi;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  release();
+  if (ms)
+    for (int32_t i = 0; i < n && i <= (int32_t)vs.size(); ++i) ms[i] = times[i];
+  if (best == -2) {
+    (void)dedisp_plan_set_adjoint_variant(p, saved);
+    return fail(DEDISP_E_UNTUNED, "no adjoint variant ran");
+  }
+  return dedisp_plan_set_adjoint_variant(p, best);
+}
+
 int32_t dedisp_autotune_times(dedisp_plan p, dedisp_dtype t, float* ms, int32_t n) {
   if (!p || !ms) return 0;
   std::vector<float>& times = last_times(p, t);

@@ -206,3 +206,23 @@ def test_autograd_against_oracle_and_fd():
         e[0, c, t] = eps
         fd = (L(x64 + e, w64) - L(x64 - e, w64)) / (2 * eps)
         assert abs(fd - gx[0, c, t]) <= 1e-3 * max(1e-3, abs(fd)), (c, t, fd, gx[0, c, t])
+
+
+def test_adjoint_autotune_keeps_a_correct_variant():
+    dd = _dd()
+    b = synth.config(0)[0]
+    plan = dd.Plan(b.freqs(), b.tsamp_s, b.dms())
+    times = plan.autotune_adjoint(2, b.nsamp)
+    _note(f"adjoint autotune: {times}")
+    assert "direct" in times and len(times) >= 3
+    chosen = plan.adjoint_variant()
+    names = dd.variant_names("f32")
+    best = min(times, key=times.get)
+    assert (best == "direct" and chosen == -1) or names[chosen] == best
+    delta = oracle.delay_table(b.freqs(), b.tsamp_s, b.dms())
+    nin = b.nsamp + int(delta.max())
+    rng = np.random.default_rng(23)
+    g = rng.standard_normal((2, b.ndm, b.nsamp)).astype(np.float32)
+    gi, _ = dd.adjoint(_rows(g), plan, nin)
+    torch.cuda.synchronize()
+    assert np.array_equal(gi.cpu().numpy(), oracle.adjoint_gather_f32(g, delta, nin))
