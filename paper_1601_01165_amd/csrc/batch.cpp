@@ -260,8 +260,7 @@ dedisp_status dedisp_batch_create(dedisp_batch* out, int32_t nbeam, const dedisp
   int vi = -1;
   if (tune) vi = tune_batch(b);
   if (vi < 0) {
-    static const int pref[] = {0, 1, 2, 4, 3, 5};
-    for (int k : pref) {
+    for (int k : default_order(0)) {
       bool ok = true;
       for (int i = 0; i < nbeam && ok; ++i) ok = ensure_tables(b->plans[i], 0, k, nullptr) == DEDISP_OK;
       if (ok) {

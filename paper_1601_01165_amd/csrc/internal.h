@@ -55,6 +55,9 @@ struct Variant {
 
 const std::vector<Variant>& variants_f32();
 const std::vector<Variant>& variants_u8();
+// Variant indices in order of preference when nothing was tuned (dir: 0 forward
+// FP32, 1 forward uint8, 2 adjoint); every index of the direction's list appears.
+const std::vector<int>& default_order(int dir);
 
 // Host-built tile tables for one variant on one delay matrix.
 //   blk[row_tile][rows_in]            {stage_base, stage_len}
