@@ -165,8 +165,9 @@ hipError_t launch_det_finish(const DetRec* recs, bool int_vals, int nseries, int
                              double* snr, int32_t* width, int32_t* start, double* mean, double* stdv, hipStream_t s);
 int batched_blocks_per_cu(const Variant& v);
 
-// Timing (tune.cpp): median of `reps` launches of fn after a warm-up launch,
-// -1 if a launch fails.
+// Timing (tune.cpp): ms per launch of fn, the median over `reps` groups of
+// back-to-back launches (about 2 ms per group, one launch for longer ones)
+// after a warm-up; -1 if a launch fails.
 float median_ms(const std::function<hipError_t()>& fn, hipStream_t s, int reps, hipEvent_t e0, hipEvent_t e1);
 
 // Fill nbytes of device memory with seeded pseudo-random data (f32: values in

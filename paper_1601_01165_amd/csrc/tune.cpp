@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <fstream>
 #include <sstream>
 #include <string>
@@ -96,17 +97,30 @@ static void cache_store(const char* path, const std::string& key, const std::str
   (void)rename(tmp.c_str(), path);
 }
 
-// Median time in ms of `reps` launches of fn after one warm-up launch.
+// Time in ms per launch of fn.  A first timed launch warms up and sizes the
+// groups: launches shorter than kGroupMs run back to back in groups of about
+// kGroupMs (after one such group as a further warm-up), so that the GPU is
+// timed busy, as in a pipeline, and not recovering from the idle gap of a
+// per-launch wait.  Returns the median over `reps` groups of the group mean.
+static constexpr float kGroupMs = 2.0f;
+
 float median_ms(const std::function<hipError_t()>& fn, hipStream_t s, int reps, hipEvent_t e0, hipEvent_t e1) {
-  if (fn() != hipSuccess) return -1.f;
+  auto timed = [&](int n, float& ms) {
+    if (hipEventRecord(e0, s) != hipSuccess) return false;
+    for (int i = 0; i < n; ++i)
+      if (fn() != hipSuccess) return false;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return false;
+    return hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+  };
+  float t1 = 0.f;
+  if (!timed(1, t1)) return -1.f;
+  const int n = t1 >= kGroupMs ? 1 : std::min(64, (int)std::ceil(kGroupMs / std::max(t1, 1e-3f)));
+  float ms = 0.f;
+  if (n > 1 && !timed(n, ms)) return -1.f;
   std::vector<float> t;
   for (int r = 0; r < reps; ++r) {
-    if (hipEventRecord(e0, s) != hipSuccess) return -1.f;
-    if (fn() != hipSuccess) return -1.f;
-    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.f;
-    float ms = 0;
-    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.f;
-    t.push_back(ms);
+    if (!timed(n, ms)) return -1.f;
+    t.push_back(ms / n);
   }
   std::sort(t.begin(), t.end());
   return t[t.size() / 2];
