@@ -255,6 +255,8 @@ def test_config1_full_size_sampled():
         synth.inject(x, delta, j, t0, b.pulse_width, b.pulse_amp)
     plan = dd.Plan(b.freqs(), b.tsamp_s, b.dms())
     _note(f"config1 default variant {plan.variant()}")
+    # untuned, the plan takes the measured-fastest shape that fits this geometry
+    assert dd.variant_names("f32")[plan.variant()] == "win_tp20_dpw8_nw8_win56_cc4_buf2"
     xg = torch.from_numpy(x).cuda()[None][:, :, :nin]
     out = dd.dedisperse(xg, plan, nsamp=b.nsamp)
     torch.cuda.synchronize()
@@ -281,6 +283,7 @@ def test_config2_full_size_sampled():
     x = synth.noise(b, nin, synth.padded_len(nin, 1))
     plan = dd.Plan(b.freqs(), b.tsamp_s, b.dms())
     _note(f"config2 default u8 variant {plan.variant('u8')}")
+    assert dd.variant_names("u8")[plan.variant("u8")] == "u8s_q4_dpw4_nw8_cc4"
     xg = torch.from_numpy(x).cuda()[None][:, :, :nin]
     out = dd.dedisperse(xg, plan, nsamp=b.nsamp)
     torch.cuda.synchronize()
