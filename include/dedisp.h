@@ -217,10 +217,13 @@ dedisp_status dedisp_batch_destroy(dedisp_batch batch);
  *   d_start  [nbeam][ndm] int32         d_mean, d_std [nbeam][ndm] double, or NULL
  *   d_workspace: device scratch of at least dedisp_detect_workspace_bytes(...)
  *            bytes, 16-byte aligned (contents on return: undefined).
- * Uses a kernel variant with the search in its epilogue: the plan's tuned
- * variant for in_type when it has one, else the first that fits (see
- * dedisp_detect_variant); when none fits it dedisperses into the workspace
- * and searches the stored rows (dedisp_detect_rows).  Asynchronous on
+ * Uses a kernel variant with the search in its epilogue: the one set with
+ * dedisp_plan_set_detect_variant or kept by dedisp_detect_autotune, else the
+ * first that fits from an order of preference measured on MI355X (see
+ * dedisp_detect_variant); when that is -1 or none fits it dedisperses into
+ * the workspace and searches the stored rows (dedisp_detect_rows).  The
+ * forward variant (dedisp_plan_set_variant, dedisp_autotune) only serves the
+ * unfused path.  Asynchronous on
  * `stream`; the first call of a plan and dtype may build tile tables
  * (allocates).
  * Errors: as dedisp_execute, plus DEDISP_E_INVALID (nwidth out of range,
