@@ -118,8 +118,9 @@ dedisp_status dedisp_plan_prepare(dedisp_plan plan, dedisp_dtype in_type, int32_
  * the default; falls back to a direct (untiled) kernel when no tiled variant
  * fits the plan's delay spans.  Asynchronous on `stream`.
  * Errors: DEDISP_E_INVALID (NULL plan or pointer, nbeam < 1, nsamp < 1),
- * DEDISP_E_DTYPE, DEDISP_E_SHAPE (in_stride < nsamp + max_delay or
- * out_stride < nsamp), DEDISP_E_ALIGN, DEDISP_E_HIP (launch failure). */
+ * DEDISP_E_DTYPE, DEDISP_E_SHAPE (in_stride < nsamp + max_delay,
+ * out_stride < nsamp, rows longer than 2^29 samples, or more than 65535
+ * beams), DEDISP_E_ALIGN, DEDISP_E_HIP (launch failure). */
 dedisp_status dedisp_execute(dedisp_plan plan, int32_t nbeam, int32_t nsamp, const void* d_in, dedisp_dtype in_type,
                              int64_t in_stride, const float* d_w, void* d_out, dedisp_dtype out_type,
                              int64_t out_stride, void* stream);

@@ -94,6 +94,7 @@ dedisp_status dedisp_detect(dedisp_plan p, int32_t nbeam, int32_t nsamp, const v
                             void* stream) {
   if (!p) return fail(DEDISP_E_INVALID, "plan is NULL");
   if (nbeam < 1 || nsamp < 1) return fail(DEDISP_E_INVALID, "nbeam and nsamp must be >= 1");
+  if (nbeam > kMaxBeams) return fail(DEDISP_E_SHAPE, "at most 65535 beams per call");
   if (!d_in) return fail(DEDISP_E_INVALID, "input pointer is NULL");
   dedisp_status st = check_outputs(nwidth, d_snr, d_width, d_start);
   if (st != DEDISP_OK) return st;

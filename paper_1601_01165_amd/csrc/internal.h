@@ -28,6 +28,8 @@ enum Kind { KIND_WIN_F32 = 0, KIND_TILE_U8 = 1 };
 // Longest row (samples) accepted: row byte sizes must fit a 32-bit buffer
 // range, and sample indices an int, with room for tile overhang.
 constexpr int64_t kMaxRow = (int64_t)1 << 29;
+// Most beams one call takes: beams are the y dimension of the launch grid.
+constexpr int kMaxBeams = 65535;
 
 struct Variant {
   const char* name;

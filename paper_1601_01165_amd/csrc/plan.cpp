@@ -387,6 +387,7 @@ dedisp_status dedisp_execute(dedisp_plan p, int32_t nbeam, int32_t nsamp, const 
                              int64_t out_stride, void* stream) {
   if (!p) return fail(DEDISP_E_INVALID, "plan is NULL");
   if (nbeam < 1 || nsamp < 1) return fail(DEDISP_E_INVALID, "nbeam and nsamp must be >= 1");
+  if (nbeam > kMaxBeams) return fail(DEDISP_E_SHAPE, "at most 65535 beams per call");
   if (!d_in || !d_out) return fail(DEDISP_E_INVALID, "input or output pointer is NULL");
   const bool f32 = in_type == DEDISP_F32 && out_type == DEDISP_F32;
   const bool u8 = in_type == DEDISP_U8 && out_type == DEDISP_I32;
@@ -456,6 +457,7 @@ dedisp_status dedisp_adjoint(dedisp_plan p, int32_t nbeam, int32_t nsamp, int32_
                              void* stream) {
   if (!p) return fail(DEDISP_E_INVALID, "plan is NULL");
   if (nbeam < 1 || nsamp < 1 || nin < 1) return fail(DEDISP_E_INVALID, "nbeam, nsamp and nin must be >= 1");
+  if (nbeam > kMaxBeams) return fail(DEDISP_E_SHAPE, "at most 65535 beams per call");
   if (!d_g) return fail(DEDISP_E_INVALID, "output gradient is NULL");
   if (!d_grad_in && !d_grad_w) return DEDISP_OK;
   if (d_grad_w && !d_in) return fail(DEDISP_E_INVALID, "grad_w needs the forward input");

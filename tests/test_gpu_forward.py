@@ -327,4 +327,17 @@ def test_errors_on_gpu():
                           out.data_ptr(), _clib.I32, out.stride(1), s)
     assert st == _clib.E_DTYPE
     assert L.dedisp_plan_set_variant(plan.handle, _clib.F32, 999) == _clib.E_INVALID
+    # empty and oversized calls are refused before any launch
+    args = (x.data_ptr(), _clib.F32, x.stride(1), None, out.data_ptr(), _clib.F32, out.stride(1), s)
+    assert L.dedisp_execute(plan.handle, 1, 0, *args) == _clib.E_INVALID
+    assert L.dedisp_execute(plan.handle, 0, b.nsamp, *args) == _clib.E_INVALID
+    assert L.dedisp_execute(plan.handle, 65536, b.nsamp, *args) == _clib.E_SHAPE
+    assert L.dedisp_execute(plan.handle, 1, b.nsamp, None, *args[1:]) == _clib.E_INVALID
+    assert L.dedisp_execute(plan.handle, 1, b.nsamp, x.data_ptr(), _clib.F32, (1 << 29) + 4, None, out.data_ptr(),
+                            _clib.F32, out.stride(1), s) == _clib.E_SHAPE
+    g = dd.empty_rows(1, b.ndm, b.nsamp, torch.float32, "cuda", zero=True)
+    nin = b.nsamp + plan.max_delay
+    gi = dd.empty_rows(1, b.nchan, nin, torch.float32, "cuda")
+    assert L.dedisp_adjoint(plan.handle, 65536, b.nsamp, nin, g.data_ptr(), g.stride(1), None, None, 0,
+                            gi.data_ptr(), gi.stride(1), None, None, 0, s) == _clib.E_SHAPE
     torch.cuda.synchronize()
