@@ -121,6 +121,20 @@ def time_cold(fn, runs, stream_sync):
     return [a.elapsed_time(b) for a, b in per]
 
 
+def cpu_model():
+    """The host CPU's model name and logical CPU count, as the OS reports them."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    name = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": name, "logical_cpus": os.cpu_count()}
+
+
 def cpu_baseline(beam, target_s, search=False):
     """Time the plain oracle on a bounded sample of one beam: all channels and
     samples, a prefix of the DM trials sized for ~target_s seconds (with
@@ -166,6 +180,7 @@ def cpu_baseline(beam, target_s, search=False):
         "unit": "DM-trial·samples/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
+        "host": cpu_model(),
         "sample": f"one beam: {beam.nchan} channels x {beam.nsamp} samples, {what} "
                   f"(Algorithm 1 order, {arith}), {el:.1f} s",
         "seconds": el,

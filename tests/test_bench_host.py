@@ -1,4 +1,4 @@
-"""Host-side checks of the benchmark script (no GPU): the one-GPU rule, and the
+"""Host-side checks of the benchmark script (no GPU): the one-GPU rule, the host description, and the
 lookup of stored HBM byte counters, which applies only to the kernel sources
 they were measured on."""
 import json
@@ -46,3 +46,10 @@ def test_stored_traffic_ignores_other_sources(tmp_path, monkeypatch):
     assert bench.stored_traffic("lofar", "v1") is None
     monkeypatch.setattr(bench, "kernel_sources_hash", lambda: "0000000000000000")
     assert bench.stored_traffic("lofar", "v1") == 1e9
+
+
+def test_cpu_model_is_reported():
+    host = bench.cpu_model()
+    assert set(host) == {"model", "logical_cpus"}
+    assert isinstance(host["model"], str) and host["model"]
+    assert host["logical_cpus"] is None or host["logical_cpus"] >= 1
