@@ -234,9 +234,13 @@ def kernel_sources_hash():
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("engine.hip", "win_asm.inc", "detect_dev.h"):
-        with open(os.path.join(ROOT, "paper_1601_01165_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_1601_01165_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        # the sources, including the generator of the inner steps (its output is not tracked)
+        if f.endswith((".hip", ".h", ".py")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode())
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -12,10 +12,13 @@
  *
  *   - Delay law: Section 2, Equation 1.  Delays are computed ahead of time
  *     (Section 2.1).
- *   - Forward dedispersion: Section 2.1, Algorithm 1 (loops dm -> sample ->
- *     chan, accumulator cleared per output).  Data are single precision
- *     (Section 2.1), so the accumulator is FP32; an FP64 twin gives the exact
- *     value and the error scale.
+ *   - Forward dedispersion: the sum that Section 2.1 (Algorithm 1) defines,
+ *     out[dm][t] = sum over channels of in[chan][t + delta[dm][chan]], with
+ *     every output receiving its terms in ascending channel order.  Data are
+ *     single precision (Section 2.1), so each output is an FP32 sum with one
+ *     rounding per term; an FP64 twin gives the exact value and the error
+ *     scale.  The loops run per output row: the row is cleared, then each
+ *     channel's shifted input row is added into it.
  *   - Adjoint: the transpose of Algorithm 1's linear map (not in the paper;
  *     derived from it), in gather form and in scatter form.
  *
@@ -100,20 +103,18 @@ void oracle_forward_f32(int nbeam, int nchan, int ndm, int nsamp, const float* i
                         const int32_t* delta, const float* w, float* out, int64_t out_stride) {
 #pragma omp parallel for collapse(2) schedule(dynamic, 1)
   for (int b = 0; b < nbeam; ++b) {
-    for (int dmi = 0; dmi < ndm; ++dmi) {
-      const float* inb = in + (size_t)b * nchan * in_stride;
-      const int32_t* drow = delta + (size_t)dmi * nchan;
-      float* orow = out + ((size_t)b * ndm + dmi) * out_stride;
-      for (int sample = 0; sample < nsamp; ++sample) {
-        float dsample = 0.0f;
-        for (int chan = 0; chan < nchan; ++chan) {
-          float x = inb[(size_t)chan * in_stride + sample + drow[chan]];
-          if (w)
-            dsample = fmaf(w[chan], x, dsample);
-          else
-            dsample = dsample + x;
+    for (int j = 0; j < ndm; ++j) {
+      float* row = out + ((size_t)b * ndm + j) * out_stride;
+      for (int t = 0; t < nsamp; ++t) row[t] = 0.0f;
+      for (int c = 0; c < nchan; ++c) {
+        /* channel c's input row, shifted by its delay at DM trial j */
+        const float* src = in + ((size_t)b * nchan + c) * in_stride + delta[(size_t)j * nchan + c];
+        if (w) {
+          const float wc = w[c];
+          for (int t = 0; t < nsamp; ++t) row[t] = fmaf(wc, src[t], row[t]);
+        } else {
+          for (int t = 0; t < nsamp; ++t) row[t] = row[t] + src[t];
         }
-        orow[sample] = dsample;
       }
     }
   }
@@ -125,39 +126,37 @@ void oracle_forward_f64(int nbeam, int nchan, int ndm, int nsamp, const double* 
                         const int32_t* delta, const double* w, double* out, double* absout, int64_t out_stride) {
 #pragma omp parallel for collapse(2) schedule(dynamic, 1)
   for (int b = 0; b < nbeam; ++b) {
-    for (int dmi = 0; dmi < ndm; ++dmi) {
-      const double* inb = in + (size_t)b * nchan * in_stride;
-      const int32_t* drow = delta + (size_t)dmi * nchan;
-      size_t o = ((size_t)b * ndm + dmi) * out_stride;
-      for (int sample = 0; sample < nsamp; ++sample) {
-        double s = 0.0, a = 0.0;
-        for (int chan = 0; chan < nchan; ++chan) {
-          double x = inb[(size_t)chan * in_stride + sample + drow[chan]];
-          double wc = w ? w[chan] : 1.0;
-          s += wc * x;
-          a += fabs(wc * x);
+    for (int j = 0; j < ndm; ++j) {
+      double* row = out + ((size_t)b * ndm + j) * out_stride;
+      double* arow = absout ? absout + ((size_t)b * ndm + j) * out_stride : NULL;
+      for (int t = 0; t < nsamp; ++t) {
+        row[t] = 0.0;
+        if (arow) arow[t] = 0.0;
+      }
+      for (int c = 0; c < nchan; ++c) {
+        const double* src = in + ((size_t)b * nchan + c) * in_stride + delta[(size_t)j * nchan + c];
+        const double wc = w ? w[c] : 1.0;
+        for (int t = 0; t < nsamp; ++t) {
+          row[t] += wc * src[t];
+          if (arow) arow[t] += fabs(wc * src[t]);
         }
-        out[o + sample] = s;
-        if (absout) absout[o + sample] = a;
       }
     }
   }
 }
 
-/* Algorithm 1 on 8-bit unsigned input with a 32-bit integer accumulator
+/* The same sum on 8-bit unsigned input with a 32-bit integer accumulator
  * (unit weights; exact). */
 void oracle_forward_u8(int nbeam, int nchan, int ndm, int nsamp, const uint8_t* in, int64_t in_stride,
                        const int32_t* delta, int32_t* out, int64_t out_stride) {
 #pragma omp parallel for collapse(2) schedule(dynamic, 1)
   for (int b = 0; b < nbeam; ++b) {
-    for (int dmi = 0; dmi < ndm; ++dmi) {
-      const uint8_t* inb = in + (size_t)b * nchan * in_stride;
-      const int32_t* drow = delta + (size_t)dmi * nchan;
-      int32_t* orow = out + ((size_t)b * ndm + dmi) * out_stride;
-      for (int sample = 0; sample < nsamp; ++sample) {
-        int32_t dsample = 0;
-        for (int chan = 0; chan < nchan; ++chan) dsample += (int32_t)inb[(size_t)chan * in_stride + sample + drow[chan]];
-        orow[sample] = dsample;
+    for (int j = 0; j < ndm; ++j) {
+      int32_t* row = out + ((size_t)b * ndm + j) * out_stride;
+      for (int t = 0; t < nsamp; ++t) row[t] = 0;
+      for (int c = 0; c < nchan; ++c) {
+        const uint8_t* src = in + ((size_t)b * nchan + c) * in_stride + delta[(size_t)j * nchan + c];
+        for (int t = 0; t < nsamp; ++t) row[t] += (int32_t)src[t];
       }
     }
   }
@@ -165,7 +164,8 @@ void oracle_forward_u8(int nbeam, int nchan, int ndm, int nsamp, const uint8_t* 
 
 /* Selected outputs, one by one, for checks at sizes where the full output is
  * too costly on the CPU.  Point p is (beam[p], dm[p], sample[p]).  Writes the
- * FP32 Algorithm 1 value and the FP64 error scale sum |w * x|. */
+ * FP32 sum (channels ascending, one rounding per term) and the FP64 error
+ * scale sum |w * x|. */
 void oracle_forward_points_f32(int nchan, const float* in, int64_t in_stride, int64_t beam_stride,
                                const int32_t* delta, const float* w, int64_t npts, const int32_t* pb,
                                const int32_t* pdm, const int32_t* ps, float* out, double* absout) {
@@ -173,19 +173,19 @@ void oracle_forward_points_f32(int nchan, const float* in, int64_t in_stride, in
   for (int64_t p = 0; p < npts; ++p) {
     const float* inb = in + (size_t)pb[p] * beam_stride;
     const int32_t* drow = delta + (size_t)pdm[p] * nchan;
-    float dsample = 0.0f;
+    float acc = 0.0f;
     double a = 0.0;
     for (int chan = 0; chan < nchan; ++chan) {
       float x = inb[(size_t)chan * in_stride + ps[p] + drow[chan]];
       if (w) {
-        dsample = fmaf(w[chan], x, dsample);
+        acc = fmaf(w[chan], x, acc);
         a += fabs((double)w[chan] * (double)x);
       } else {
-        dsample = dsample + x;
+        acc = acc + x;
         a += fabs((double)x);
       }
     }
-    out[p] = dsample;
+    out[p] = acc;
     if (absout) absout[p] = a;
   }
 }
@@ -197,9 +197,9 @@ void oracle_forward_points_u8(int nchan, const uint8_t* in, int64_t in_stride, i
   for (int64_t p = 0; p < npts; ++p) {
     const uint8_t* inb = in + (size_t)pb[p] * beam_stride;
     const int32_t* drow = delta + (size_t)pdm[p] * nchan;
-    int32_t dsample = 0;
-    for (int chan = 0; chan < nchan; ++chan) dsample += (int32_t)inb[(size_t)chan * in_stride + ps[p] + drow[chan]];
-    out[p] = dsample;
+    int32_t acc = 0;
+    for (int chan = 0; chan < nchan; ++chan) acc += (int32_t)inb[(size_t)chan * in_stride + ps[p] + drow[chan]];
+    out[p] = acc;
   }
 }
 

@@ -181,6 +181,34 @@ def test_forward_fp32_within_summation_bound():
     assert np.abs(o32 - o64).max() > 0  # FP32 really is FP32
 
 
+@pytest.mark.parametrize("weighted", [False, True])
+def test_forward_fp32_order_per_output_bruteforce(weighted):
+    """Each output is the sequential FP32 sum of its terms in ascending channel
+    order, one rounding per term (Section 2.1, single precision): a pure-Python
+    loop over one output at a time, on real-valued data where the order
+    changes the rounding.  Weights are powers of two, so w * x is exact and the
+    fused multiply-add is one FP32 add of the product."""
+    rng = np.random.default_rng(21)
+    nc, nd, ns, nb = 9, 5, 23, 2
+    delta, nin = _rand_case(rng, nc, nd, ns, 10)
+    x = (rng.standard_normal((nb, nc, nin)) * 10.0 ** rng.integers(-3, 4, (nb, nc, nin))).astype(np.float32)
+    w = (2.0 ** rng.integers(-2, 3, nc)).astype(np.float32) if weighted else None
+    out = oracle.forward_f32(x, delta, ns, w)
+    for b in range(nb):
+        for j in range(nd):
+            for t in range(ns):
+                acc = np.float32(0.0)
+                for c in range(nc):
+                    term = x[b, c, t + delta[j, c]]
+                    if w is not None:
+                        term = np.float32(w[c] * term)
+                    acc = np.float32(acc + term)
+                assert out[b, j, t] == acc, (b, j, t)
+    # a different channel order rounds differently somewhere (the pin can fail)
+    rev = oracle.forward_f32(x[:, ::-1].copy(), delta[:, ::-1].copy(), ns, None if w is None else w[::-1].copy())
+    assert not np.array_equal(rev, out)
+
+
 def test_forward_dm0_is_channel_sum():
     rng = np.random.default_rng(1)
     b = synth.config(0)[0]
