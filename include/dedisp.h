@@ -158,18 +158,32 @@ size_t dedisp_adjoint_workspace_bytes(dedisp_plan plan, int32_t nbeam, int32_t n
 /* ------------------------------------------------------------------------ */
 
 /* Describe nbeam independent beams, each with its own plan (channel count,
- * DM list), output length nsamp[i], float32 input d_in[i] (stride
- * in_stride[i]), weights d_w[i] (or NULL) and output d_out[i] (stride
- * out_stride[i]); the same validity rules as dedisp_execute apply to every
- * beam.  Chooses one tiled kernel variant for all beams (the fastest measured
- * one when tune != 0, else the default), builds a device work table of all
- * tiles ordered by decreasing cost, and prepares a persistent kernel.  The
- * arrays are copied; plans must outlive the batch.  Allocates; not for use
- * under graph capture. */
+ * DM list), output length nsamp[i], input d_in[i] of type in_t (stride
+ * in_stride[i] elements), weights d_w[i] (or NULL) and float32 output
+ * d_out[i] (stride out_stride[i]); the same validity rules as dedisp_execute
+ * apply to every beam.  Only in_t = DEDISP_F32 is supported (DEDISP_E_DTYPE
+ * otherwise): the persistent kernel is the FP32 tile engine.
+ *
+ * Chooses the tiled kernel variant(s) and builds a device work table of all
+ * tiles ordered by decreasing cost for one persistent kernel.  With tune != 0
+ * every candidate is timed on the batch's own buffers (their contents are
+ * overwritten) and the fastest kept (Section 2.2 and Section 4.1: the best
+ * configuration depends on the platform and the set-up); with tune_cache
+ * non-NULL the choice is looked up in, and stored to, that JSON file, keyed
+ * by the device, the weights flag and the multiset of beam set-ups (channel
+ * count, DM count, output length rounded up to a power of two, hash of the
+ * delay table), so a later batch of the same shapes skips the search.
+ * tune == 0 takes the first default variant that fits every beam.  The
+ * arrays are copied; plans and buffers must outlive the batch (the captured
+ * graph keeps their addresses).  Allocates; not for use under graph capture. */
 dedisp_status dedisp_batch_create(dedisp_batch* batch, int32_t nbeam, const dedisp_plan* plans,
-                                  const int32_t* nsamp, const float* const* d_in, const int64_t* in_stride,
-                                  const float* const* d_w, float* const* d_out, const int64_t* out_stride,
-                                  int32_t tune);
+                                  const int32_t* nsamp, const void* const* d_in, dedisp_dtype in_t,
+                                  const int64_t* in_stride, const float* const* d_w, void* const* d_out,
+                                  const int64_t* out_stride, int32_t tune, const char* tune_cache);
+
+/* 1 if the batch's variant came from its tune cache, 0 if it was searched
+ * or defaulted, -1 for a NULL batch. */
+int32_t dedisp_batch_cache_hit(dedisp_batch batch);
 
 /* Run every beam of the batch: one persistent launch that walks the work
  * table.  The first call captures the launch into a HIP graph; later calls
@@ -191,6 +205,7 @@ dedisp_status dedisp_batch_set_variant(dedisp_batch batch, int32_t variant);
 /* The tiled variant the batch runs (-1 for a NULL batch). */
 int32_t dedisp_batch_variant(dedisp_batch batch);
 
+/* Wait for any replay of the batch still in flight, then free it. */
 dedisp_status dedisp_batch_destroy(dedisp_batch batch);
 
 /* ------------------------------------------------------------------------ */

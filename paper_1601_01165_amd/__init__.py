@@ -364,35 +364,76 @@ def dedisperse_autograd(x, plan, w=None, nsamp=None):
     return DedispFunction.apply(x, w, plan, nsamp)
 
 
+def _check_batch_beam(i: int, plan, x, o, nsamp: int, w) -> None:
+    """Refuse a batch beam whose buffers do not match its plan.  Runs before
+    any library call: the persistent launch sees only pointers, and the
+    captured graph keeps them, so nothing may be copied or re-laid out."""
+    at = f"beam {i}: "
+    if x.dim() != 3 or x.shape[0] != 1 or o.dim() != 3 or o.shape[0] != 1:
+        raise ValueError(at + "inputs and outputs are single beams [1][rows][samples]")
+    if x.shape[1] != plan.nchan:
+        raise ValueError(at + f"input has {x.shape[1]} channels, plan has {plan.nchan}")
+    if o.shape[1] != plan.ndm:
+        raise ValueError(at + f"output has {o.shape[1]} DM rows, plan has {plan.ndm}")
+    if not 1 <= nsamp <= o.shape[2]:
+        raise ValueError(at + f"nsamp {nsamp} outside 1..{o.shape[2]} (output row length)")
+    if x.shape[2] < nsamp + plan.max_delay:
+        raise ValueError(at + f"input rows hold {x.shape[2]} samples, need nsamp + max_delay = "
+                         f"{nsamp + plan.max_delay}")
+    if x.dtype != torch.float32 or o.dtype != torch.float32:
+        raise ValueError(at + "batches take float32 input and output")
+    if w is not None and (w.dim() != 1 or w.numel() != plan.nchan or w.dtype != torch.float32
+                          or w.stride(0) != 1):
+        raise ValueError(at + "weights must be a contiguous float32 tensor of nchan values")
+    if not _rows_ok(x) or not _rows_ok(o):
+        raise ValueError(at + "rows must start on 16-byte boundaries with 16-byte multiple strides "
+                         "(allocate them with empty_rows); batches never copy their buffers")
+    if not x.is_cuda or not o.is_cuda or (w is not None and not w.is_cuda):
+        raise ValueError(at + "input, output and weights must be on the GPU")
+
+
 class Batch:
     """Many independent beams (each its own plan, sizes and buffers) run as one
     persistent, graph-captured launch (execute) or as a per-beam launch loop
-    (execute_per_beam)."""
+    (execute_per_beam).  Buffers are used in place: the caller may refill them
+    between calls, and they must stay alive while the batch exists.
 
-    def __init__(self, plans, inputs, outputs, nsamps=None, weights=None, tune=False):
+    tune: time the candidate kernel variants on the batch's own buffers and
+    keep the fastest (overwrites the outputs); tune_cache: a JSON file in which
+    that choice is looked up first and stored afterwards."""
+
+    def __init__(self, plans, inputs, outputs, nsamps=None, weights=None, tune=False, tune_cache=None):
         L = lib()
         n = len(plans)
         if not (len(inputs) == len(outputs) == n) or n < 1:
             raise ValueError("plans, inputs and outputs must have the same non-zero length")
-        xs = [_as_rows(x) for x in inputs]
-        for x, o in zip(xs, outputs):
-            if x.shape[0] != 1 or o.dim() != 3 or o.shape[0] != 1 or not _rows_ok(o):
-                raise ValueError("batch inputs/outputs are single beams with 16-byte aligned rows")
+        if weights is not None and len(weights) != n:
+            raise ValueError("weights must have one entry per beam")
+        xs = [x.unsqueeze(0) if x.dim() == 2 else x for x in inputs]
+        os_ = [o.unsqueeze(0) if o.dim() == 2 else o for o in outputs]
         if nsamps is None:
-            nsamps = [o.shape[2] for o in outputs]
-        self._keep = (plans, xs, outputs, weights)
+            nsamps = [o.shape[2] for o in os_]
+        for i in range(n):
+            _check_batch_beam(i, plans[i], xs[i], os_[i], int(nsamps[i]),
+                              None if weights is None else weights[i])
+        self._keep = (plans, xs, os_, weights)
         arr = lambda typ, vals: (typ * n)(*vals)  # noqa: E731
         hp = arr(ctypes.c_void_p, [p.handle.value for p in plans])
-        ns = arr(ctypes.c_int32, nsamps)
+        ns = arr(ctypes.c_int32, [int(v) for v in nsamps])
         din = arr(ctypes.c_void_p, [x.data_ptr() for x in xs])
         ist = arr(ctypes.c_int64, [x.stride(1) for x in xs])
         dw = arr(ctypes.c_void_p, [w.data_ptr() for w in weights]) if weights is not None else None
-        dout = arr(ctypes.c_void_p, [o.data_ptr() for o in outputs])
-        ost = arr(ctypes.c_int64, [o.stride(1) for o in outputs])
+        dout = arr(ctypes.c_void_p, [o.data_ptr() for o in os_])
+        ost = arr(ctypes.c_int64, [o.stride(1) for o in os_])
         h = ctypes.c_void_p()
-        check(L.dedisp_batch_create(ctypes.byref(h), n, hp, ns, din, ist, dw, dout, ost, int(bool(tune))),
-              "batch_create")
+        check(L.dedisp_batch_create(ctypes.byref(h), n, hp, ns, din, F32, ist, dw, dout, ost, int(bool(tune)),
+                                    tune_cache.encode() if tune_cache else None), "batch_create")
         self._h = h
+
+    @property
+    def cache_hit(self) -> bool:
+        """True if the variant came from the tune cache (no search ran)."""
+        return int(lib().dedisp_batch_cache_hit(self._h)) == 1
 
     def execute(self):
         check(lib().dedisp_execute_batched(self._h, _stream()), "execute_batched")

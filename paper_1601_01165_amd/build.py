@@ -1,6 +1,9 @@
 """Build libdedisp.so (gfx950) in-tree with hipcc.
 
-Usage: python -m paper_1601_01165_amd.build [--force]
+Usage: python -m paper_1601_01165_amd.build [--incremental]
+
+By default every source is compiled.  --incremental recompiles only the
+objects older than their source or any shared header (a development aid).
 """
 from __future__ import annotations
 
@@ -40,8 +43,18 @@ def _gen():
                    check=True)
 
 
-def _compile(src: str) -> str:
+def _stale(src: str, obj: str) -> bool:
+    if not os.path.exists(obj):
+        return True
+    deps = [os.path.join(CSRC, src), os.path.join(INCLUDE, "dedisp.h")]
+    deps += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".h", ".inc"))]
+    return os.path.getmtime(obj) < max(os.path.getmtime(d) for d in deps)
+
+
+def _compile(src: str, force: bool = True) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
+    if not force and not _stale(src, obj):
+        return obj
     cmd = [HIPCC, *DEVICE_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC, *DEVICE_FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
@@ -56,7 +69,7 @@ def build(force: bool = True) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     _gen()
     with ThreadPoolExecutor(max_workers=4) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda f: _compile(f, force), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -76,4 +89,4 @@ def device_asm(src: str = "engine.hip") -> str:
 
 
 if __name__ == "__main__":
-    print(build())
+    print(build(force="--incremental" not in sys.argv[1:]))

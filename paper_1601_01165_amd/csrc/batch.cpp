@@ -3,6 +3,7 @@
 // tile of every beam, largest tiles first, and is captured once into a HIP
 // graph that later calls replay.
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -37,13 +38,26 @@ struct dedisp_batch_s {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;  // recorded after every replay
+  bool launched = false;
+  int cache_hit = 0;
 };
 
 static void drop_work(dedisp_batch b);
 
+// Wait until no replay of the batch's graph is in flight.
+static hipError_t wait_idle(dedisp_batch b) {
+  if (!b->launched || !b->done) return hipSuccess;
+  const hipError_t e = hipEventSynchronize(b->done);
+  if (e == hipSuccess) b->launched = false;
+  return e;
+}
+
 static void batch_free(dedisp_batch b) {
   if (!b) return;
+  (void)wait_idle(b);
   drop_work(b);
+  if (b->done) (void)hipEventDestroy(b->done);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   delete b;
 }
@@ -170,7 +184,7 @@ static dedisp_status build_work(dedisp_batch b, int vi) {
 // and return the fastest, or -1; then time the winner with one queue per XCD
 // and keep that split if it is faster.  Leaves the batch without a work
 // table.
-static int tune_batch(dedisp_batch b) {
+static int tune_batch(dedisp_batch b, float* best_out) {
   const std::vector<Variant>& vs = variants_f32();
   hipStream_t s = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -219,8 +233,12 @@ static int tune_batch(dedisp_batch b) {
           },
           s, 2, e0, e1);
     }
-    if (!(ms > 0 && ms < best_ms)) b->nqueue = 1;
+    if (!(ms > 0 && ms < best_ms))
+      b->nqueue = 1;
+    else
+      best_ms = ms;
   }
+  if (best_out) *best_out = best_ms;
   drop_work(b);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -228,37 +246,108 @@ static int tune_batch(dedisp_batch b) {
   return best;
 }
 
+// Tune-cache key of a batch: the device, the weights flag and the multiset of
+// beam set-ups (channels, DM trials, output length rounded up to a power of
+// two, delay-table hash), hashed in sorted order.
+static std::string batch_cache_key(dedisp_batch b) {
+  std::vector<std::string> items;
+  for (int i = 0; i < b->nbeam; ++i) {
+    int bucket = 1;
+    while (bucket < b->nsamp[i]) bucket <<= 1;
+    char buf[96];
+    snprintf(buf, sizeof(buf), "%d/%d/%d/%016llx", b->plans[i]->nchan, b->plans[i]->ndm, bucket,
+             (unsigned long long)delay_table_hash(b->plans[i]));
+    items.push_back(buf);
+  }
+  std::sort(items.begin(), items.end());
+  uint64_t h = 1469598103934665603ull;
+  for (const std::string& it : items)
+    for (char c : it + ";") {
+      h ^= (unsigned char)c;
+      h *= 1099511628211ull;
+    }
+  char key[192];
+  snprintf(key, sizeof(key), "%s|batch|f32|w%d|n%d|h%016llx", tune_device_name().c_str(), b->d_w[0] != nullptr,
+           b->nbeam, (unsigned long long)h);
+  return key;
+}
+
+// Cached choice "variant name" or "variant name|q8" (one queue per XCD).
+static int parse_cached(const std::string& v, int& nqueue) {
+  std::string name = v;
+  nqueue = 1;
+  const size_t bar = v.find('|');
+  if (bar != std::string::npos) {
+    name = v.substr(0, bar);
+    if (v.substr(bar + 1) == "q8") nqueue = kNumXcd;
+  }
+  const std::vector<Variant>& vs = variants_f32();
+  for (int i = 0; i < (int)vs.size(); ++i)
+    if (name == vs[i].name) return i;
+  return -1;
+}
+
 extern "C" {
 
 dedisp_status dedisp_batch_create(dedisp_batch* out, int32_t nbeam, const dedisp_plan* plans, const int32_t* nsamp,
-                                  const float* const* d_in, const int64_t* in_stride, const float* const* d_w,
-                                  float* const* d_out, const int64_t* out_stride, int32_t tune) {
+                                  const void* const* d_in, dedisp_dtype in_t, const int64_t* in_stride,
+                                  const float* const* d_w, void* const* d_out, const int64_t* out_stride, int32_t tune,
+                                  const char* tune_cache) {
   if (!out) return fail(DEDISP_E_INVALID, "batch pointer is NULL");
   *out = nullptr;
   if (nbeam < 1) return fail(DEDISP_E_INVALID, "nbeam must be >= 1");
   if (!plans || !nsamp || !d_in || !in_stride || !d_out || !out_stride)
     return fail(DEDISP_E_INVALID, "a per-beam array is NULL");
+  if (in_t != DEDISP_F32) return fail(DEDISP_E_DTYPE, "batches take float32 input only");
   dedisp_batch b = new (std::nothrow) dedisp_batch_s();
   if (!b) return fail(DEDISP_E_NOMEM, "host allocation failed");
   b->nbeam = nbeam;
   for (int i = 0; i < nbeam; ++i) {
     const float* w = d_w ? d_w[i] : nullptr;
-    dedisp_status st = check_beam(i, plans[i], nsamp[i], d_in[i], in_stride[i], w, d_out[i], out_stride[i]);
+    const float* xin = static_cast<const float*>(d_in[i]);
+    float* xout = static_cast<float*>(d_out[i]);
+    dedisp_status st = check_beam(i, plans[i], nsamp[i], xin, in_stride[i], w, xout, out_stride[i]);
     if (st != DEDISP_OK) {
       batch_free(b);
       return st;
     }
     b->plans.push_back(plans[i]);
     b->nsamp.push_back(nsamp[i]);
-    b->d_in.push_back(d_in[i]);
+    b->d_in.push_back(xin);
     b->in_stride.push_back(in_stride[i]);
     b->d_w.push_back(w);
-    b->d_out.push_back(d_out[i]);
+    b->d_out.push_back(xout);
     b->out_stride.push_back(out_stride[i]);
   }
-  // Variant: the tuned choice, or the first default that fits every beam.
+  for (int i = 1; i < nbeam; ++i)
+    if ((b->d_w[i] != nullptr) != (b->d_w[0] != nullptr)) {
+      batch_free(b);
+      return fail(DEDISP_E_INVALID, "weights must be given for all beams or none");
+    }
+  // Variant: the cached or tuned choice, or the first default that fits every beam.
   int vi = -1;
-  if (tune) vi = tune_batch(b);
+  if (tune) {
+    const std::string key = batch_cache_key(b);
+    std::string hit;
+    if (tune_cache_lookup(tune_cache, key, hit)) {
+      int nq = 1;
+      const int ci = parse_cached(hit, nq);
+      bool ok = ci >= 0;
+      for (int i = 0; i < nbeam && ok; ++i) ok = ensure_tables(b->plans[i], 0, ci, nullptr) == DEDISP_OK;
+      if (ok) {
+        vi = ci;
+        b->nqueue = nq;
+        b->cache_hit = 1;
+      }
+    }
+    if (vi < 0) {
+      float ms = -1.f;
+      vi = tune_batch(b, &ms);
+      if (vi >= 0)
+        tune_cache_store(tune_cache, key,
+                         std::string(variants_f32()[vi].name) + (b->nqueue == kNumXcd ? "|q8" : ""), ms);
+    }
+  }
   if (vi < 0) {
     for (int k : default_order(0)) {
       bool ok = true;
@@ -279,6 +368,7 @@ dedisp_status dedisp_batch_create(dedisp_batch* out, int32_t nbeam, const dedisp
     return st;
   }
   hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
   if (e != hipSuccess) {
     batch_free(b);
     return hip_fail(e, "creating the capture stream");
@@ -310,7 +400,11 @@ dedisp_status dedisp_execute_batched(dedisp_batch b, void* stream) {
     }
   }
   e = hipGraphLaunch(b->exec, (hipStream_t)stream);
-  return e == hipSuccess ? DEDISP_OK : hip_fail(e, "launching the graph");
+  if (e != hipSuccess) return hip_fail(e, "launching the graph");
+  e = hipEventRecord(b->done, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "recording the replay's completion event");
+  b->launched = true;
+  return DEDISP_OK;
 }
 
 dedisp_status dedisp_execute_per_beam(dedisp_batch b, void* stream) {
@@ -331,13 +425,15 @@ dedisp_status dedisp_batch_set_variant(dedisp_batch b, int32_t variant) {
     dedisp_status st = ensure_tables(b->plans[i], 0, variant, nullptr);
     if (st != DEDISP_OK) return st;
   }
-  const hipError_t e = hipDeviceSynchronize();  // no replay of the old graph is in flight
-  if (e != hipSuccess) return hip_fail(e, "synchronizing before a variant change");
+  const hipError_t e = wait_idle(b);  // no replay of the old graph is in flight
+  if (e != hipSuccess) return hip_fail(e, "waiting for the batch before a variant change");
   drop_work(b);
   return build_work(b, variant);
 }
 
 int32_t dedisp_batch_variant(dedisp_batch b) { return b ? b->variant : -1; }
+
+int32_t dedisp_batch_cache_hit(dedisp_batch b) { return b ? b->cache_hit : -1; }
 
 dedisp_status dedisp_batch_destroy(dedisp_batch b) {
   batch_free(b);

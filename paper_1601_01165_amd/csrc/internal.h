@@ -172,6 +172,13 @@ int batched_blocks_per_cu(const Variant& v);
 // after a warm-up; -1 if a launch fails.
 float median_ms(const std::function<hipError_t()>& fn, hipStream_t s, int reps, hipEvent_t e0, hipEvent_t e1);
 
+// Tuning cache (tune.cpp): a JSON file of {"key": {"variant": "...", "ms": t}}
+// lines.  The device's architecture name, a hash of a plan's delay table.
+std::string tune_device_name();
+uint64_t delay_table_hash(dedisp_plan p);
+bool tune_cache_lookup(const char* path, const std::string& key, std::string& value);
+void tune_cache_store(const char* path, const std::string& key, const std::string& value, float ms);
+
 // Fill nbytes of device memory with seeded pseudo-random data (f32: values in
 // [-1, 1); otherwise bytes), for timing on realistic inputs.
 hipError_t launch_fill_random(void* p, size_t nbytes, bool f32, uint32_t seed, hipStream_t s);

@@ -20,7 +20,7 @@ namespace dd {
 dedisp_status ensure_tables(dedisp_plan p, int dir, int vi, Tables** out);
 
 // FNV-1a over the delay table: two plans with equal tables share tuning.
-static uint64_t table_hash(dedisp_plan p) {
+uint64_t delay_table_hash(dedisp_plan p) {
   uint64_t h = 1469598103934665603ull;
   const unsigned char* b = reinterpret_cast<const unsigned char*>(p->delay.data());
   const size_t n = p->delay.size() * sizeof(int32_t);
@@ -31,7 +31,7 @@ static uint64_t table_hash(dedisp_plan p) {
   return h;
 }
 
-static std::string device_name() {
+std::string tune_device_name() {
   int dev = 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
@@ -45,14 +45,14 @@ static std::string cache_key(dedisp_plan p, dedisp_dtype t, int nbeam, int nsamp
   int bucket = 1;
   while (bucket < nsamp) bucket <<= 1;
   char buf[256];
-  snprintf(buf, sizeof(buf), "%s|%s|c%d|d%d|s%d|b%d|h%016llx", device_name().c_str(), t == DEDISP_U8 ? "u8" : "f32",
-           p->nchan, p->ndm, bucket, nbeam, (unsigned long long)table_hash(p));
+  snprintf(buf, sizeof(buf), "%s|%s|c%d|d%d|s%d|b%d|h%016llx", tune_device_name().c_str(), t == DEDISP_U8 ? "u8" : "f32",
+           p->nchan, p->ndm, bucket, nbeam, (unsigned long long)delay_table_hash(p));
   return buf;
 }
 
 // Cache file: a JSON object, one entry per line:
 //   "key": {"variant": "name", "ms": 1.234},
-static bool cache_lookup(const char* path, const std::string& key, std::string& variant) {
+bool tune_cache_lookup(const char* path, const std::string& key, std::string& variant) {
   if (!path) return false;
   std::ifstream f(path);
   if (!f) return false;
@@ -70,7 +70,7 @@ static bool cache_lookup(const char* path, const std::string& key, std::string& 
   return false;
 }
 
-static void cache_store(const char* path, const std::string& key, const std::string& variant, float ms) {
+void tune_cache_store(const char* path, const std::string& key, const std::string& variant, float ms) {
   if (!path) return;
   std::vector<std::string> entries;
   {
@@ -150,7 +150,7 @@ dedisp_status dedisp_autotune(dedisp_plan p, int32_t nbeam, int32_t nsamp, dedis
   const std::vector<Variant>& vs = u8 ? variants_u8() : variants_f32();
   const std::string key = cache_key(p, t, nbeam, nsamp);
   std::string hit;
-  if (cache_lookup(cache_path, key, hit)) {
+  if (tune_cache_lookup(cache_path, key, hit)) {
     if (hit == "direct") return dedisp_plan_set_variant(p, t, -1);
     for (int i = 0; i < (int)vs.size(); ++i)
       if (hit == vs[i].name && dedisp_plan_set_variant(p, t, i) == DEDISP_OK) return DEDISP_OK;
@@ -209,7 +209,7 @@ dedisp_status dedisp_autotune(dedisp_plan p, int32_t nbeam, int32_t nsamp, dedis
   }
   dedisp_status st = dedisp_plan_set_variant(p, t, best);
   if (st != DEDISP_OK) return st;
-  cache_store(cache_path, key, best < 0 ? "direct" : vs[best].name, best_ms);
+  tune_cache_store(cache_path, key, best < 0 ? "direct" : vs[best].name, best_ms);
   return DEDISP_OK;
 }
 

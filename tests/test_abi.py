@@ -146,3 +146,51 @@ def test_detect_argument_checks(clib):
     assert rows(2, 10, E.F32, 12, 6, ws=None) == E.E_WORKSPACE
     assert rows(2, 10, E.F32, 12, 6, ws=ctypes.c_void_p(4104)) == E.E_ALIGN
     assert rows(2, 10, E.F32, 12, 6, wsb=64) == E.E_WORKSPACE
+
+
+class _FakePlan:
+    """Stand-in for a Plan (the batch checks read only its sizes)."""
+
+    nchan, ndm, max_delay = 8, 5, 30
+
+
+def _aligned(shape, dtype="float32"):
+    import torch
+
+    dt = getattr(torch, dtype)
+    es = torch.empty((), dtype=dt).element_size()
+    q = 16 // es
+    n = (shape[2] + q - 1) // q * q
+    return torch.zeros((shape[0], shape[1], n), dtype=dt)[:, :, : shape[2]]
+
+
+def test_batch_beam_checks_refuse_before_any_launch():
+    """Every mismatch between a batch beam's buffers and its plan is refused
+    on the host, before the library sees the pointers."""
+    import torch
+
+    import paper_1601_01165_amd as dd
+
+    p = _FakePlan()
+    x = _aligned((1, 8, 130))
+    o = _aligned((1, 5, 100))
+    chk = dd._check_batch_beam
+    cases = [
+        ((_aligned((1, 7, 130)), o, 100, None), "channels"),
+        ((x, _aligned((1, 6, 100)), 100, None), "DM rows"),
+        ((x, o, 101, None), "nsamp"),
+        ((x, o, 0, None), "nsamp"),
+        ((_aligned((1, 8, 129)), o, 100, None), "max_delay"),
+        ((_aligned((1, 8, 130), "uint8"), o, 100, None), "float32"),
+        ((x, _aligned((1, 5, 100), "int32"), 100, None), "float32"),
+        ((x, o, 100, torch.ones(7)), "weights"),
+        ((x, o, 100, torch.ones(8, dtype=torch.float64)), "weights"),
+        ((torch.zeros((1, 8, 131))[:, :, :130], o, 100, None), "16-byte"),   # row stride 131 floats
+        ((x, torch.zeros((1, 5, 101))[:, :, :100], 100, None), "16-byte"),
+        ((torch.zeros((1, 8, 133))[:, :, 1:131], o, 100, None), "16-byte"),  # base off by 4 bytes
+        ((x, o, 100, None), "GPU"),                                          # right shapes, host memory
+        ((x, o, 100, torch.ones(8)), "GPU"),
+    ]
+    for args, what in cases:
+        with pytest.raises(ValueError, match=what):
+            chk(0, p, *args)

@@ -214,3 +214,57 @@ def test_config3_full_size_sampled():
         got = outs[i][0].cpu().numpy()[pd, ps]
         _note(f"config3 beam {i}: {b.nchan} ch, {b.ndm} DMs, {b.nsamp} samples")
         assert np.array_equal(got, ref), f"beam {i}"
+
+
+def test_batched_tune_cache_hit(tmp_path):
+    """The batch's tuning is stored in the cache file and a second batch of
+    the same shapes takes it from there (no search), with the same variant and
+    results still equal to the oracle."""
+    dd = _dd()
+    cache = str(tmp_path / "batch_tune.json")
+    beams = _small_batch(4, seed=47)
+    plans, xs, outs, ref_in, deltas, _ = _setup(beams)
+    _note("tuned batch, cold cache")
+    b1 = dd.Batch(plans, xs, outs, tune=True, tune_cache=cache)
+    assert not b1.cache_hit
+    v1 = b1.variant
+    assert "|batch|f32|w0|n4|" in open(cache).read()
+    _note("tuned batch, warm cache")
+    b2 = dd.Batch(plans, xs, outs, tune=True, tune_cache=cache)
+    assert b2.cache_hit and b2.variant == v1
+    for o in outs:
+        o.fill_(float("nan"))
+    b2.execute()
+    torch.cuda.synchronize()
+    for i, b in enumerate(beams):
+        assert np.array_equal(outs[i].cpu().numpy(), oracle.forward_f32(ref_in[i], deltas[i], b.nsamp)), i
+    # other shapes miss the cache
+    beams3 = _small_batch(3, seed=53)
+    plans3, xs3, outs3, _, _, _ = _setup(beams3)
+    assert not dd.Batch(plans3, xs3, outs3, tune=True, tune_cache=cache).cache_hit
+
+
+def test_batched_refuses_uint8_and_bad_beams():
+    """uint8 batches are refused by the C-ABI with the dtype status; buffers
+    that do not match their plan are refused before the library is called."""
+    dd = _dd()
+    from paper_1601_01165_amd import _clib
+    import ctypes
+
+    beams = _small_batch(2, seed=59)
+    plans, xs, outs, _, _, _ = _setup(beams)
+    L = dd.lib()
+    n = 2
+    arr = lambda typ, vals: (typ * n)(*vals)  # noqa: E731
+    h = ctypes.c_void_p()
+    st = L.dedisp_batch_create(ctypes.byref(h), n, arr(ctypes.c_void_p, [p.handle.value for p in plans]),
+                               arr(ctypes.c_int32, [b.nsamp for b in beams]),
+                               arr(ctypes.c_void_p, [x.data_ptr() for x in xs]), _clib.U8,
+                               arr(ctypes.c_int64, [x.stride(1) for x in xs]), None,
+                               arr(ctypes.c_void_p, [o.data_ptr() for o in outs]),
+                               arr(ctypes.c_int64, [o.stride(1) for o in outs]), 0, None)
+    assert st == _clib.E_DTYPE
+    with pytest.raises(ValueError, match="DM rows"):
+        dd.Batch(plans, xs, outs[::-1])
+    with pytest.raises(ValueError, match="GPU"):
+        dd.Batch(plans, xs, outs, weights=[torch.ones(p.nchan) for p in plans])

@@ -341,3 +341,106 @@ def test_errors_on_gpu():
     assert L.dedisp_adjoint(plan.handle, 65536, b.nsamp, nin, g.data_ptr(), g.stride(1), None, None, 0,
                             gi.data_ptr(), gi.stride(1), None, None, 0, s) == _clib.E_SHAPE
     torch.cuda.synchronize()
+
+
+def _seq_channel_sum(x2, ns, w=None):
+    """Sequential FP32 sum over channels (ascending, one rounding per term),
+    written independently of the oracle: the value every DM-0 output takes."""
+    acc = np.zeros(ns, np.float32)
+    for c in range(x2.shape[0]):
+        term = x2[c, :ns] if w is None else (w[c] * x2[c, :ns]).astype(np.float32)
+        acc = (acc + term).astype(np.float32)
+    return acc
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_perfect_reuse_all_zero_dms_f32(weighted):
+    """The perfect-reuse set-up of Section 4.3: every DM trial is 0, so every
+    delay span is 0 and every trial reads the same samples.  Every FP32
+    variant and the direct kernel, against the oracle bit for bit, and every
+    row equal to the sequential channel sum.  Weights are powers of two so
+    that w * x is exact and the weighted sum is still a sequential FP32 sum."""
+    dd = _dd()
+    b = synth.config(1)[0]
+    f = b.freqs()[::4]  # 256 channels of the Apertif-like band
+    ns, nd = 2049, 97
+    dms = np.zeros(nd)
+    delta = oracle.delay_table(f, b.tsamp_s, dms)
+    assert (delta == 0).all()
+    rng = np.random.default_rng(81)
+    x = rng.standard_normal((2, f.size, ns + 3)).astype(np.float32)
+    w = (2.0 ** rng.integers(-2, 3, f.size)).astype(np.float32) if weighted else None
+    plan = dd.Plan(f, b.tsamp_s, dms)
+    assert plan.max_delay == 0
+    xg = _to_gpu(x)
+    wg = torch.from_numpy(w).cuda() if weighted else None
+    rows = [_seq_channel_sum(x[k], ns, w) for k in range(2)]
+    vs = _variants(plan, "f32")
+    assert len(vs) == len(dd.variant_names("f32")) + 1  # zero spans fit every variant
+    for v in vs:
+        _note(f"perfect reuse f32 variant {v} weighted={weighted}")
+        plan.set_variant(v)
+        out = dd.dedisperse(xg, plan, wg, nsamp=ns)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        _check_f32(got, x, delta, ns, w, where=f"perfect reuse v{v}")
+        for k in range(2):
+            assert (got[k] == rows[k][None, :]).all(), (v, k)
+
+
+def test_perfect_reuse_and_dm_runs_u8():
+    """uint8: all-zero DM trials (every row the integer channel sum) and a DM
+    list made of long runs of equal values (equal trials give equal rows),
+    every uint8 variant and the direct kernel, bit-exact against the oracle."""
+    dd = _dd()
+    b = synth.config(2)[0]
+    ns = 3001
+    rng = np.random.default_rng(83)
+    runs = np.concatenate([np.zeros(40), np.full(25, 0.5), np.full(31, 0.51), np.full(9, 3.0),
+                           np.arange(12) * 0.01 + 1.0, np.full(20, 1.11)])
+    for name, dms in (("zero", np.zeros(64)), ("runs", runs)):
+        delta = oracle.delay_table(b.freqs(), b.tsamp_s, dms)
+        nin = ns + int(delta.max())
+        x = rng.integers(0, 256, size=(1, b.nchan, nin)).astype(np.uint8)
+        ref = oracle.forward_u8(x, delta, ns)
+        plan = dd.Plan(b.freqs(), b.tsamp_s, dms)
+        xg = _to_gpu(x, pad_extra=16)
+        chan_sum = x[0, :, :ns].astype(np.int64).sum(axis=0)
+        for v in _variants(plan, "u8"):
+            _note(f"u8 {name} variant {v}")
+            plan.set_variant(v, "u8")
+            out = dd.dedisperse(xg, plan, nsamp=ns)
+            torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            assert np.array_equal(got, ref), (name, v)
+            if name == "zero":
+                assert (got[0] == chan_sum[None, :]).all(), v
+            for j in range(1, dms.size):
+                if dms[j] == dms[j - 1]:
+                    assert np.array_equal(got[0, j], got[0, j - 1]), (name, v, j)
+
+
+def test_dm_runs_f32():
+    """FP32 with a DM list of long runs of equal trials (and a few isolated
+    ones): every variant bit for bit against the oracle, equal trials equal."""
+    dd = _dd()
+    b = synth.config(1)[0]
+    f = b.freqs()[::8]
+    runs = np.concatenate([np.zeros(33), np.full(40, 12.25), np.array([12.5, 13.0]), np.full(27, 100.0),
+                           np.full(5, 100.25), np.full(21, 300.0)])
+    delta = oracle.delay_table(f, b.tsamp_s, runs)
+    ns = 1800
+    rng = np.random.default_rng(85)
+    x = rng.standard_normal((1, f.size, ns + int(delta.max()))).astype(np.float32)
+    plan = dd.Plan(f, b.tsamp_s, runs)
+    xg = _to_gpu(x)
+    for v in _variants(plan, "f32"):
+        _note(f"dm runs f32 variant {v}")
+        plan.set_variant(v)
+        out = dd.dedisperse(xg, plan, nsamp=ns)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        _check_f32(got, x, delta, ns, where=f"dm runs v{v}")
+        for j in range(1, runs.size):
+            if runs[j] == runs[j - 1]:
+                assert np.array_equal(got[0, j], got[0, j - 1]), (v, j)
