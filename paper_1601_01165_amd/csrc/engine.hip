@@ -47,6 +47,15 @@ __device__ __forceinline__ int xcd_remap(int L, int N) {
 
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
+// The lane index, recomputed where it is used: the asm keeps the compiler
+// from hoisting lane-dependent offsets out of loops and holding them in
+// registers the small register windows cannot spare.
+__device__ __forceinline__ int lane_fresh() {
+  int l;
+  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+  return l;
+}
+
 // A pointer the compiler must keep in SGPRs (its value is wave-uniform).
 template <typename T>
 __device__ __forceinline__ T* uniform_ptr(T* p) {
@@ -114,7 +123,7 @@ __device__ __forceinline__ float sload_f32(const float* p) {
 template <int NWAVE, int ROWCAP>
 __device__ __forceinline__ void stage_f32(float4* lds4, const float* in, const TileArgs& a, const int32_t* blk,
                                           int c0, int ncc, int t0) {
-  const int wave = wave_id(), lane = threadIdx.x & 63;
+  const int wave = wave_id(), lane = lane_fresh();
   for (int cl = wave; cl < ncc; cl += NWAVE) {
     const int sb = blk[2 * (c0 + cl)];
     const int sl = blk[2 * (c0 + cl) + 1];
@@ -148,11 +157,47 @@ __device__ __forceinline__ void stage_f32_async(float4* lds4, const float* in, c
                                                 const int32_t* blk, int c0, int ncc, int t0) {
   // whole 64-lane loads stay inside the row's LDS slot
   static_assert(ROWCAP % 256 == 0, "LDS rows hold a multiple of 64 float4");
-  const int wave = wave_id(), lane = threadIdx.x & 63;
+  const int wave = wave_id(), lane = lane_fresh();
   for (int cl = wave; cl < ncc; cl += NWAVE) {
     const ent2_t bl = sload_entry2(blk + 2 * (c0 + cl));
     const int sb = bl[0];
     const int sl = bl[1];
+    const float* base = in + (int64_t)(c0 + cl) * a.in_stride + a.in_lo + a.in_shift;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (a.in_hi - a.in_lo) * 4, 0x00020000);
+    const int u0 = t0 + sb - a.in_lo;
+    const int nv = sl >> 2;
+    for (int v0 = 0; v0 < nv; v0 += 64) {
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (LDS_AS void*)(lds4 + cl * (ROWCAP / 4) + v0), 16,
+                                               (u0 + 4 * (v0 + lane)) * 4, 0, 0, 0);
+    }
+  }
+}
+
+// Entries {stage base, stage length} of the rows wave w stages for the pass
+// starting at input row c0 (rows w, w + NWAVE, ...): lane 2k holds the base
+// of the wave's k-th row, lane 2k + 1 its length.  A vector load, issued a
+// pass ahead: the per-pass wait for the staged rows covers it, so staging
+// never stalls on a scalar-cache miss.
+template <int NWAVE, int CC>
+__device__ __forceinline__ int32_t stage_entries(const int32_t* blk, int rows_in, int c0) {
+  constexpr int RPW = (CC + NWAVE - 1) / NWAVE;
+  const int wave = wave_id(), lane = lane_fresh();
+  const int cl = wave + (lane >> 1) * NWAVE;
+  if (lane < 2 * RPW && cl < CC && c0 + cl < rows_in) return blk[2 * (c0 + cl) + (lane & 1)];
+  return 0;
+}
+
+// stage_f32_async with the entries from stage_entries (no scalar loads).
+template <int NWAVE, int ROWCAP>
+__device__ __forceinline__ void stage_f32_async_pre(float4* lds4, const float* in, const TileArgs& a, int32_t ent,
+                                                    int c0, int ncc, int t0) {
+  static_assert(ROWCAP % 256 == 0, "LDS rows hold a multiple of 64 float4");
+  const int wave = wave_id();
+  for (int k = 0, cl = wave; cl < ncc; ++k, cl += NWAVE) {
+    const int lane = lane_fresh();
+    const int sb = __builtin_amdgcn_readlane(ent, 2 * k);
+    const int sl = __builtin_amdgcn_readlane(ent, 2 * k + 1);
     const float* base = in + (int64_t)(c0 + cl) * a.in_stride + a.in_lo + a.in_shift;
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (a.in_hi - a.in_lo) * 4, 0x00020000);
@@ -173,7 +218,7 @@ template <int NWAVE, int ROWCAP>
 __device__ __forceinline__ void fix_tail_async(float4* lds4, const float* in, const TileArgs& a,
                                                const int32_t* blk, int c0, int ncc, int t0) {
   if ((a.in_hi & 3) == 0) return;
-  const int wave = wave_id(), lane = threadIdx.x & 63;
+  const int wave = wave_id(), lane = lane_fresh();
   const int hi4 = a.in_hi & ~3;
   for (int cl = wave; cl < ncc; cl += NWAVE) {
     const ent2_t bl = sload_entry2(blk + 2 * (c0 + cl));
@@ -196,7 +241,7 @@ template <int TP, int DPW, int NWAVE, bool ADJ>
 __device__ __forceinline__ void win_store(const TileArgs& a, const v16f* acc, int tt, int rt, int beam) {
   constexpr int DT = NWAVE * DPW;
   const int t0 = tt * 64 * TP;
-  const int wave = wave_id(), lane = threadIdx.x & 63;
+  const int wave = wave_id(), lane = lane_fresh();
   float* out = static_cast<float*>(a.out);
   const int tl = t0 + lane * TP;
 #pragma unroll
@@ -266,7 +311,7 @@ template <int TP, int DPW, int NWAVE>
 __device__ __forceinline__ void det_store_f32(const TileArgs& a, const v16f* acc, int tt, int rt, int beam, int t0) {
   constexpr int ST = 64 * TP;
   constexpr int DT = NWAVE * DPW;
-  const int wave = wave_id(), lane = threadIdx.x & 63;
+  const int wave = wave_id(), lane = lane_fresh();
   const int nvalid = min(ST, a.det_nsamp - t0);
   const int pos0 = TP * lane;
   const bool owned = pos0 < a.tile_step;
@@ -296,14 +341,16 @@ __device__ __forceinline__ void det_store_f32(const TileArgs& a, const v16f* acc
 // NBUF = 2: asynchronous LDS loads into two buffers; the rows of pass p + 1
 // are in flight while pass p is summed.
 template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool WEIGHTED, bool ADJ,
-          bool DET = false>
+          bool DET = false, int JMP = 0>
 __device__ __forceinline__ void win_tile(const TileArgs& a, int tt, int rt, int beam, float4* lds4) {
   constexpr int ST = 64 * TP;
   constexpr int DT = NWAVE * DPW;
   constexpr int NACC = TP * DPW / 16;
   constexpr int WI = EntT<DPW>::ints;
+  tt = __builtin_amdgcn_readfirstlane(tt);
+  rt = __builtin_amdgcn_readfirstlane(rt);
   const int t0 = DET ? tt * a.tile_step : tt * ST;
-  const int wave = wave_id(), lane = threadIdx.x & 63;
+  const int wave = wave_id();
   const int wt = rt * NWAVE + wave;
   const float* in = static_cast<const float*>(a.in) + (int64_t)beam * a.in_beam_stride;
   const int32_t* __restrict__ blk = uniform_ptr(a.blk + (size_t)rt * a.rows_in * 2);
@@ -327,12 +374,12 @@ __device__ __forceinline__ void win_tile(const TileArgs& a, int tt, int rt, int 
   E ea = sload_entry_t<E>(wav), eb;
   float wa = WEIGHTED ? sload_f32(w_in) : 0.f, wb = 0.f;
   const int npass = (a.rows_in + CC - 1) / CC;
+  int32_t stg = 0;  // staging entries of the next pass (NBUF = 2)
   if (NBUF == 2) {
     __syncthreads();  // a previous tile of this block is done with the LDS rows
     stage_f32_async<NWAVE, ROWCAP>(lds4, in, a, blk, 0, min(CC, a.rows_in), t0);
+    if (CC < a.rows_in) stg = stage_entries<NWAVE, CC>(blk, a.rows_in, CC);
   }
-  // LDS byte address of this lane's window in row slot 0 of buffer 0
-  const uint32_t lane_base = lds_base + (uint32_t)(lane * TP * 4);
   for (int p = 0; p < npass; ++p) {
     const int c0 = p * CC;
     const int ncc = min(CC, a.rows_in - c0);
@@ -346,11 +393,17 @@ __device__ __forceinline__ void win_tile(const TileArgs& a, int tt, int rt, int 
       fix_tail_async<NWAVE, ROWCAP>(lds4 + (p & 1) * CC * (ROWCAP / 4), in, a, blk, c0, ncc, t0);
       __syncthreads();  // every wave's have; every wave is done with pass p - 1
       if (p + 1 < npass)
-        stage_f32_async<NWAVE, ROWCAP>(lds4 + ((p + 1) & 1) * CC * (ROWCAP / 4), in, a, blk, c0 + CC,
-                                       min(CC, a.rows_in - c0 - CC), t0);
+        stage_f32_async_pre<NWAVE, ROWCAP>(lds4 + ((p + 1) & 1) * CC * (ROWCAP / 4), in, a, stg, c0 + CC,
+                                           min(CC, a.rows_in - c0 - CC), t0);
+      if (p + 2 < npass) stg = stage_entries<NWAVE, CC>(blk, a.rows_in, c0 + 2 * CC);
     }
-    uint32_t row = lane_base + (uint32_t)(bufrow * ROWCAP * 4);
-    if constexpr (HasWinPass<TP, DPW, NWIN, CC>::value) {
+    // LDS byte address of this lane's window in the pass's first row slot
+    uint32_t row = lds_base + (uint32_t)(lane_fresh() * TP * 4) + (uint32_t)(bufrow * ROWCAP * 4);
+    if constexpr (JMP) {
+      // the whole pass in one block, each row's DM slots branching into static adds
+      static_assert(HasJmpPass<TP, DPW, NWIN, CC>::value, "no jump-form pass for this shape");
+      JmpPass<TP, DPW, NWIN, CC, WEIGHTED, JMP == 2, ROWCAP>::run(acc, row, ncc, ea, trs, toff, wa, wrs, woff);
+    } else if constexpr (HasWinPass<TP, DPW, NWIN, CC>::value) {
       // the whole pass in one block, index mode on throughout
       WinPass<TP, DPW, NWIN, CC, WEIGHTED, ROWCAP>::run(acc, row, ncc, ea, trs, toff, wa, wrs, woff);
     } else {
@@ -377,14 +430,29 @@ __device__ __forceinline__ void win_tile(const TileArgs& a, int tt, int rt, int 
     win_store<TP, DPW, NWAVE, ADJ>(a, acc, tt, rt, beam);
 }
 
+// Waves per SIMD that a jump-form variant's registers allow (its accumulators
+// start at JmpAcc0, the window follows them), asked of the compiler so that it
+// keeps the rest of the kernel within that budget; 1 (no request) otherwise,
+// and for the search epilogue, whose registers would otherwise spill.
+template <int TP, int DPW, int NWIN, int CC, int JMP, bool DET = false>
+constexpr int win_waves_per_eu() {
+  if constexpr (JMP != 0 && !DET) {
+    constexpr int regs = (JmpAcc0<TP, DPW, NWIN, CC>::value + TP * DPW + NWIN + 7) / 8 * 8;
+    return 512 / regs > 8 ? 8 : 512 / regs;
+  } else {
+    return 1;
+  }
+}
+
 template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool WEIGHTED, bool ADJ,
-          bool DET = false>
-__global__ __launch_bounds__(64 * NWAVE) void win_kernel(TileArgs a) {
+          bool DET = false, int JMP = 0>
+__global__ __launch_bounds__(64 * NWAVE)
+__attribute__((amdgpu_waves_per_eu(win_waves_per_eu<TP, DPW, NWIN, CC, JMP, DET>()))) void win_kernel(TileArgs a) {
   __shared__ float4 lds4[NBUF * CC * ROWCAP / 4];
   const int nblk = a.n_time_tiles * a.n_row_tiles;
   const int W = xcd_remap(blockIdx.x, nblk);
-  win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, WEIGHTED, ADJ, DET>(a, W / a.n_row_tiles, W % a.n_row_tiles,
-                                                                        blockIdx.y, lds4);
+  win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, WEIGHTED, ADJ, DET, JMP>(a, W / a.n_row_tiles,
+                                                                             W % a.n_row_tiles, blockIdx.y, lds4);
 }
 
 // Persistent form for batches of beams.  The work table is split into one
@@ -395,8 +463,9 @@ __global__ __launch_bounds__(64 * NWAVE) void win_kernel(TileArgs a) {
 // Every beam shares the variant; per-beam pointers and tables come from its
 // descriptor.  The counters (one per queue, 128 bytes apart) are cleared by a
 // separate kernel before each launch.
-template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool WEIGHTED>
-__global__ __launch_bounds__(64 * NWAVE) void win_persistent(const BeamDesc* __restrict__ beams,
+template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool WEIGHTED, int JMP>
+__global__ __launch_bounds__(64 * NWAVE) __attribute__((amdgpu_waves_per_eu(win_waves_per_eu<TP, DPW, NWIN, CC, JMP>())))
+void win_persistent(const BeamDesc* __restrict__ beams,
                                                              const int32_t* __restrict__ order,
                                                              const int32_t* __restrict__ qoff, int* counters) {
   __shared__ float4 lds4[NBUF * CC * ROWCAP / 4];
@@ -409,13 +478,13 @@ __global__ __launch_bounds__(64 * NWAVE) void win_persistent(const BeamDesc* __r
       __syncthreads();  // everyone is done with s_tile and the LDS rows
       if (threadIdx.x == 0) s_tile = atomicAdd(counters + q * kCounterStride, 1);
       __syncthreads();
-      const int k = s_tile;
+      const int k = __builtin_amdgcn_readfirstlane(s_tile);
       if (k >= n) break;
       const int b = order[2 * (q0 + k)];
       const int local = order[2 * (q0 + k) + 1];
       const TileArgs& a = beams[b].a;
       const int tt = local / a.n_row_tiles, rt = local % a.n_row_tiles;
-      win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, WEIGHTED, false>(a, tt, rt, 0, lds4);
+      win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, WEIGHTED, false, false, JMP>(a, tt, rt, 0, lds4);
     }
   }
 }
@@ -1001,29 +1070,48 @@ __global__ __launch_bounds__(256) void reduce_gradw_kernel(const double* __restr
 // Variant tables and launchers.
 // ---------------------------------------------------------------------------
 // (index, TP samples per lane, DPW rows per wave, NWAVE, NWIN window registers,
-//  CC rows per LDS pass, ROWCAP floats per LDS row, NBUF LDS buffers)
+//  CC rows per LDS pass, ROWCAP floats per LDS row, NBUF LDS buffers, JMP)
+// JMP = 1: each row's DM slots branch into static blocks of adds (JmpPass)
+// instead of indexing the window registers; JMP = 2: the same, every row
+// reading the whole window (no per-row read-count branches).
 // A lane owns TP consecutive samples; TP/4 odd (12, 20, 28, 36) keeps its
 // 16-byte LDS reads free of bank conflicts.
 #define F32_VARIANTS(X)                                          \
-  X(0, 12, 4, 4, 36, 8, 1024, 1)   /* 16 DMs x 768             */ \
-  X(1, 12, 4, 4, 48, 8, 1024, 1)   /* 16 DMs x 768, wide spans */ \
-  X(2, 8, 8, 4, 64, 8, 1024, 1)    /* 32 DMs x 512             */ \
-  X(3, 16, 8, 4, 72, 8, 2048, 1)   /* 32 DMs x 1024            */ \
-  X(4, 8, 4, 4, 48, 16, 1024, 1)   /* 16 DMs x 512             */ \
-  X(5, 16, 4, 4, 64, 8, 2048, 1)   /* 16 DMs x 1024            */ \
-  X(6, 12, 4, 4, 36, 4, 1024, 2)   /* 16 DMs x 768, async      */ \
-  X(7, 12, 8, 4, 56, 4, 1024, 2)   /* 32 DMs x 768, async      */ \
-  X(8, 20, 4, 4, 44, 4, 1536, 2)   /* 16 DMs x 1280, async     */ \
-  X(9, 12, 4, 8, 36, 4, 1024, 2)   /* 32 DMs x 768, async      */ \
-  X(10, 12, 8, 8, 56, 4, 1280, 2)  /* 64 DMs x 768, async      */ \
-  X(11, 12, 4, 4, 48, 4, 1024, 2)  /* 16 DMs x 768, async      */ \
-  X(12, 8, 8, 4, 64, 4, 1024, 2)   /* 32 DMs x 512, async      */ \
-  X(13, 20, 8, 4, 56, 4, 1536, 2)  /* 32 DMs x 1280, async     */ \
-  X(14, 28, 4, 4, 48, 4, 2048, 2)  /* 16 DMs x 1792, async     */ \
-  X(15, 20, 8, 8, 56, 4, 1792, 2)  /* 64 DMs x 1280, async     */ \
-  X(16, 28, 4, 8, 48, 4, 2048, 2)  /* 32 DMs x 1792, async     */ \
-  X(17, 20, 8, 8, 56, 8, 1792, 2)  /* 64 DMs x 1280, async     */ \
-  X(18, 20, 8, 4, 56, 6, 1536, 2)  /* 32 DMs x 1280, async     */
+  X(0, 12, 4, 4, 36, 8, 1024, 1, 0)   /* 16 DMs x 768             */ \
+  X(1, 12, 4, 4, 48, 8, 1024, 1, 0)   /* 16 DMs x 768, wide spans */ \
+  X(2, 8, 8, 4, 64, 8, 1024, 1, 0)    /* 32 DMs x 512             */ \
+  X(3, 16, 8, 4, 72, 8, 2048, 1, 0)   /* 32 DMs x 1024            */ \
+  X(4, 8, 4, 4, 48, 16, 1024, 1, 0)   /* 16 DMs x 512             */ \
+  X(5, 16, 4, 4, 64, 8, 2048, 1, 0)   /* 16 DMs x 1024            */ \
+  X(6, 12, 4, 4, 36, 4, 1024, 2, 0)   /* 16 DMs x 768, async      */ \
+  X(7, 12, 8, 4, 56, 4, 1024, 2, 0)   /* 32 DMs x 768, async      */ \
+  X(8, 20, 4, 4, 44, 4, 1536, 2, 0)   /* 16 DMs x 1280, async     */ \
+  X(9, 12, 4, 8, 36, 4, 1024, 2, 0)   /* 32 DMs x 768, async      */ \
+  X(10, 12, 8, 8, 56, 4, 1280, 2, 0)  /* 64 DMs x 768, async      */ \
+  X(11, 12, 4, 4, 48, 4, 1024, 2, 0)  /* 16 DMs x 768, async      */ \
+  X(12, 8, 8, 4, 64, 4, 1024, 2, 0)   /* 32 DMs x 512, async      */ \
+  X(13, 20, 8, 4, 56, 4, 1536, 2, 0)  /* 32 DMs x 1280, async     */ \
+  X(14, 28, 4, 4, 48, 4, 2048, 2, 0)  /* 16 DMs x 1792, async     */ \
+  X(15, 20, 8, 8, 56, 4, 1792, 2, 0)  /* 64 DMs x 1280, async     */ \
+  X(16, 28, 4, 8, 48, 4, 2048, 2, 0)  /* 32 DMs x 1792, async     */ \
+  X(17, 20, 8, 8, 56, 8, 1792, 2, 0)  /* 64 DMs x 1280, async     */ \
+  X(18, 20, 8, 4, 56, 6, 1536, 2, 0)  /* 32 DMs x 1280, async     */ \
+  X(19, 20, 4, 6, 44, 4, 1536, 2, 1)  /* 24 DMs x 1280, jump      */ \
+  X(20, 20, 4, 4, 44, 4, 1536, 2, 1)  /* 16 DMs x 1280, jump      */ \
+  X(21, 20, 4, 12, 44, 4, 1792, 2, 1) /* 48 DMs x 1280, jump      */ \
+  X(22, 20, 8, 4, 56, 6, 1536, 2, 1)  /* 32 DMs x 1280, jump      */ \
+  X(23, 20, 8, 8, 56, 4, 1792, 2, 1)  /* 64 DMs x 1280, jump      */ \
+  X(24, 28, 4, 4, 48, 4, 2048, 2, 1)  /* 16 DMs x 1792, jump      */ \
+  X(25, 28, 4, 8, 48, 4, 2048, 2, 1)  /* 32 DMs x 1792, jump      */ \
+  X(26, 12, 4, 8, 36, 4, 1024, 2, 1)  /* 32 DMs x 768, jump       */ \
+  X(27, 12, 4, 12, 36, 4, 1024, 2, 1) /* 48 DMs x 768, jump       */ \
+  X(28, 20, 8, 4, 56, 6, 1536, 2, 2)  /* 32 DMs x 1280, jump full */ \
+  X(29, 20, 4, 12, 44, 4, 1792, 2, 2) /* 48 DMs x 1280, jump full */ \
+  X(30, 20, 4, 4, 44, 4, 1536, 2, 2)  /* 16 DMs x 1280, jump full */ \
+  X(31, 20, 8, 8, 56, 4, 1792, 2, 2)  /* 64 DMs x 1280, jump full */ \
+  X(32, 20, 4, 8, 40, 6, 1536, 2, 1)  /* 32 DMs x 1280, jump, 4 waves/SIMD */ \
+  X(33, 20, 4, 4, 40, 3, 1536, 2, 1)  /* 16 DMs x 1280, jump, 4 waves/SIMD */ \
+  X(34, 20, 4, 16, 40, 8, 1792, 2, 1) /* 64 DMs x 1280, jump, 4 waves/SIMD */
 
 // (index, Q dwords per lane, DPW, NWAVE, CC rows per LDS pass, ROWCAP bytes)
 #define U8_VARIANTS(X)                                      \
@@ -1056,9 +1144,11 @@ __global__ __launch_bounds__(256) void reduce_gradw_kernel(const double* __restr
 const std::vector<Variant>& variants_f32() {
   static const std::vector<Variant> v = [] {
     std::vector<Variant> r;
-#define MAKE_F32(ID, TP, DPW, NW, NWIN, CC, RC, NB)                                                         \
-  r.push_back(Variant{"win_tp" #TP "_dpw" #DPW "_nw" #NW "_win" #NWIN "_cc" #CC "_buf" #NB, KIND_WIN_F32, TP,   \
-                      DPW, NW, NWIN, CC, RC, NB, ID});
+#define MAKE_F32(ID, TP, DPW, NW, NWIN, CC, RC, NB, JMP)                                                    \
+  r.push_back(Variant{JMP == 2 ? "win_tp" #TP "_dpw" #DPW "_nw" #NW "_win" #NWIN "_cc" #CC "_buf" #NB "_jmpf"   \
+                      : JMP    ? "win_tp" #TP "_dpw" #DPW "_nw" #NW "_win" #NWIN "_cc" #CC "_buf" #NB "_jmp"    \
+                               : "win_tp" #TP "_dpw" #DPW "_nw" #NW "_win" #NWIN "_cc" #CC "_buf" #NB,         \
+                      KIND_WIN_F32, TP, DPW, NW, NWIN, CC, RC, NB, ID, 0, JMP});
     F32_VARIANTS(MAKE_F32)
 #undef MAKE_F32
     return r;
@@ -1095,15 +1185,18 @@ hipError_t launch_tiled(const Variant& v, const TileArgs& a, int nbeam, bool adj
   const dim3 block(64 * v.nwave);
   const bool weighted = adjoint ? false : (a.w_in != nullptr);
   if (v.kind == KIND_WIN_F32) {
-#define LAUNCH_F32(ID, TP, DPW, NW, NWIN, CC, RC, NB)                                                     \
-  if (v.id == ID) {                                                                                       \
-    if (adjoint)                                                                                          \
-      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, false, true>), grid, block, 0, s, a); \
-    else if (weighted)                                                                                    \
-      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, true, false>), grid, block, 0, s, a); \
-    else                                                                                                  \
-      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, false, false>), grid, block, 0, s, a); \
-    return hipGetLastError();                                                                             \
+#define LAUNCH_F32(ID, TP, DPW, NW, NWIN, CC, RC, NB, JMP)                                                      \
+  if (v.id == ID) {                                                                                             \
+    if (adjoint)                                                                                                \
+      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, false, true, false, JMP>), grid, block, 0, s, \
+                         a);                                                                                    \
+    else if (weighted)                                                                                          \
+      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, true, false, false, JMP>), grid, block, 0, s, \
+                         a);                                                                                    \
+    else                                                                                                        \
+      hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, false, false, false, JMP>), grid, block, 0,   \
+                         s, a);                                                                                 \
+    return hipGetLastError();                                                                                   \
   }
     F32_VARIANTS(LAUNCH_F32)
 #undef LAUNCH_F32
@@ -1145,14 +1238,15 @@ hipError_t launch_detect(const Variant& v, const TileArgs& a, int nbeam, hipStre
   const dim3 grid((unsigned)nblk, (unsigned)nbeam);
   const dim3 block(64 * v.nwave);
   if (v.kind == KIND_WIN_F32) {
-#define LAUNCH_DF(ID, TP, DPW, NW, NWIN, CC, RC, NB)                                                          \
+#define LAUNCH_DF(ID, TP, DPW, NW, NWIN, CC, RC, NB, JMP)                                                   \
   if constexpr (ID >= 13 && NB == 2) {                                                                        \
     if (v.id == ID) {                                                                                         \
       if (a.w_in)                                                                                             \
-        hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, true, false, true>), grid, block, 0, s, a); \
+        hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, true, false, true, JMP>), grid, block, 0, \
+                           s, a);                                                                             \
       else                                                                                                    \
-        hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, false, false, true>), grid, block, 0, s,  \
-                           a);                                                                                \
+        hipLaunchKernelGGL((win_kernel<TP, DPW, NW, NWIN, CC, RC, NB, false, false, true, JMP>), grid, block,   \
+                           0, s, a);                                                                          \
       return hipGetLastError();                                                                               \
     }                                                                                                         \
   }
@@ -1173,15 +1267,15 @@ hipError_t launch_detect(const Variant& v, const TileArgs& a, int nbeam, hipStre
 hipError_t launch_batched(const Variant& v, const BeamDesc* d_beams, bool weighted, const int32_t* d_order,
                           const int32_t* d_qoff, int* d_counter, int grid, hipStream_t s) {
   const dim3 block(64 * v.nwave);
-#define LAUNCH_P(ID, TP, DPW, NW, NWIN, CC, RC, NB)                                                        \
-  if (v.id == ID) {                                                                                        \
-    if (weighted)                                                                                          \
-      hipLaunchKernelGGL((win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, true>), dim3(grid), block, 0, s,  \
-                         d_beams, d_order, d_qoff, d_counter);                                             \
-    else                                                                                                   \
-      hipLaunchKernelGGL((win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, false>), dim3(grid), block, 0, s, \
-                         d_beams, d_order, d_qoff, d_counter);                                             \
-    return hipGetLastError();                                                                              \
+#define LAUNCH_P(ID, TP, DPW, NW, NWIN, CC, RC, NB, JMP)                                                    \
+  if (v.id == ID) {                                                                                          \
+    if (weighted)                                                                                            \
+      hipLaunchKernelGGL((win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, true, JMP>), dim3(grid), block, 0, s,  \
+                         d_beams, d_order, d_qoff, d_counter);                                               \
+    else                                                                                                     \
+      hipLaunchKernelGGL((win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, false, JMP>), dim3(grid), block, 0, s, \
+                         d_beams, d_order, d_qoff, d_counter);                                               \
+    return hipGetLastError();                                                                                \
   }
   if (v.kind == KIND_WIN_F32) {
     F32_VARIANTS(LAUNCH_P)
@@ -1192,9 +1286,9 @@ hipError_t launch_batched(const Variant& v, const BeamDesc* d_beams, bool weight
 
 int batched_blocks_per_cu(const Variant& v) {
   int n = 0;
-#define OCC_P(ID, TP, DPW, NW, NWIN, CC, RC, NB)                                                                 \
+#define OCC_P(ID, TP, DPW, NW, NWIN, CC, RC, NB, JMP)                                                            \
   if (v.id == ID) {                                                                                              \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, false>,  \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, win_persistent<TP, DPW, NW, NWIN, CC, RC, NB, false, JMP>, \
                                                      64 * NW, 0) != hipSuccess)                                   \
       n = 1;                                                                                                     \
     return n > 0 ? n : 1;                                                                                        \

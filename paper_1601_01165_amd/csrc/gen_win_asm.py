@@ -232,6 +232,191 @@ def pass_block(tp, dpw, nwin, cc, weighted):
     )
 
 
+def jmp_block_bytes(tp):
+    """Bytes of one static block of the jump form: TP two-operand adds (or
+    fmacs) of 4 bytes each and the 4-byte jump to the next block."""
+    return 4 * tp + 4
+
+
+def jmp_pass(tp, dpw, nwin, cc, weighted, full=False, acc0=ACC0):
+    """Specialisation of JmpPass: the rows of one LDS pass without VGPR index
+    mode.  Each DM slot j has a region of static blocks, one per window
+    offset o (0 <= o <= NWIN - TP); block (j, o) adds window registers
+    o .. o + TP - 1 into slot j's accumulators and jumps to slot j + 1's
+    chosen block (the last slot returns).  Per row the table entry holds, for
+    every slot, the byte offset o * BLK of its block inside the slot's region,
+    so a row costs one scalar add and one jump per slot instead of indexed
+    operands (which issue about 1.7 times slower on gfx950).  A slot's target
+    is its own region's base plus the entry's offset: whatever the entry
+    holds, slot j can only reach slot j's blocks, so the chain always moves on
+    to the next slot.
+
+    The targets' high words are the region's when the region does not cross
+    a 4 GB boundary (checked once per pass); otherwise a second copy of the
+    rows propagates the carries.  Entry sets alternate between two fixed
+    SGPR ranges as in the index-mode pass.  The accumulators start at
+    v[acc0]: a low acc0 leaves the fewest registers to the compiler and lets
+    small shapes reach 4 waves per SIMD."""
+    nacc = tp * dpw
+    w0 = acc0 + nacc
+    assert w0 + nwin <= 256
+    nmin = tp // 4 + 1
+    nmax = nwin // 4
+    ent = entry_ints(dpw)
+    noff = nwin - tp + 1
+    blk = jmp_block_bytes(tp)
+    slot = noff * blk
+    region = dpw * slot
+    # an entry's dpw + 2 used ints load as power-of-two pieces (4-aligned
+    # destinations for 4 and 8 dwords)
+    used = dpw + 2
+    pieces = []
+    k = 0
+    for n in (8, 4, 2, 1):
+        while used - k >= n:
+            pieces.append((k, n))
+            k += n
+    sa = SGPR_A                # set A: bound to the C++ entry (ent ints)
+    sb = sa + ent              # set B: used ints only, clobbered
+    tg = sb + ((used + 1) // 2) * 2   # targets: one SGPR pair per slot
+    sl = tg + 2 * dpw          # low word of each slot's region base
+    ret = sl + dpw + (dpw % 2)
+    base = ret + 2
+    wreg = base + 2            # weight of the row being summed (weighted form)
+    top = wreg + (1 if weighted else 0)
+    # s100 and up are reserved on gfx950
+    assert top <= 96 and tg % 2 == 0 and ret % 2 == 0 and base % 2 == 0 and sb % 4 == 0
+
+    def load_entry(dst):
+        for k0, n in pieces:
+            op = "s_buffer_load_dword" if n == 1 else f"s_buffer_load_dwordx{n}"
+            reg = f"s{dst + k0}" if n == 1 else f"s[{dst + k0}:{dst + k0 + n - 1}]"
+            L.append(f"{op} {reg}, %[trs], %[toff] offset:{4 * k0}")
+        L.append(f"s_add_u32 %[toff], %[toff], {4 * ent}")
+
+    L = [f"s_getpc_b64 s[{base}:{base + 1}]", ".Lpc_%=:",
+         f"s_add_u32 s{base}, s{base}, .Lregion_%= - .Lpc_%=",
+         f"s_addc_u32 s{base + 1}, s{base + 1}, 0"]
+    for j in range(dpw):
+        L.append(f"s_add_u32 s{sl + j}, s{base}, {j * slot}")
+    # carry out of the region's last byte: take the rows that propagate it
+    L.append(f"s_add_u32 s{ret}, s{base}, {region}")
+    L.append("s_cbranch_scc1 .Lslow_%=")
+    for j in range(dpw):
+        L.append(f"s_mov_b32 s{tg + 2 * j + 1}, s{base + 1}")
+
+    def rows(path):
+        for r in range(cc):
+            X, Y = (sa, sb) if r % 2 == 0 else (sb, sa)
+            wX, wY = ("%[wa]", "%[wb]") if r % 2 == 0 else ("%[wb]", "%[wa]")
+            L.append(f"s_lshl_b32 %[t], s{X}, 2")
+            L.append("v_add_u32 %[va], %[t], %[vrow]")
+            for k in range(nmin):
+                L.append(f"ds_read_b128 v[{w0 + 4 * k}:{w0 + 4 * k + 3}], %[va] offset:{16 * k}")
+            for k in range(nmin, nmax):
+                if not full:
+                    L.append(f"s_cmp_le_u32 s{X + 1}, {k}")
+                    L.append(f"s_cbranch_scc1 .L{path}{r}_loaded_%=")
+                L.append(f"ds_read_b128 v[{w0 + 4 * k}:{w0 + 4 * k + 3}], %[va] offset:{16 * k}")
+            L.append(f".L{path}{r}_loaded_%=:")
+            L.append("s_waitcnt lgkmcnt(0)")
+            load_entry(Y)
+            if weighted:
+                L.append(f"s_mov_b32 s{wreg}, {wX}")
+                L.append(f"s_buffer_load_dword {wY}, %[wrs], %[woff]")
+                L.append("s_add_u32 %[woff], %[woff], 4")
+            for j in range(dpw):
+                if path == "f":
+                    L.append(f"s_add_u32 s{tg + 2 * j}, s{sl + j}, s{X + 2 + j}")
+                else:
+                    L.append(f"s_add_u32 s{tg + 2 * j}, s{base}, s{X + 2 + j}")
+                    L.append(f"s_addc_u32 s{tg + 2 * j + 1}, s{base + 1}, 0")
+                    L.append(f"s_add_u32 s{tg + 2 * j}, s{tg + 2 * j}, {j * slot}")
+                    L.append(f"s_addc_u32 s{tg + 2 * j + 1}, s{tg + 2 * j + 1}, 0")
+            L.append(f"s_swappc_b64 s[{ret}:{ret + 1}], s[{tg}:{tg + 1}]")
+            L.append("v_add_u32 %[vrow], %[rowbytes], %[vrow]")
+            L.append("s_waitcnt lgkmcnt(0)")
+            if r + 1 < cc:
+                L.append(f"s_cmp_le_u32 %[ncc], {r + 1}")
+                L.append(f"s_cbranch_scc1 {'.Lcopy_%=' if r % 2 == 0 else '.Lend_%='}")
+        if cc % 2 == 0:  # after the last (odd) row the next entry is already in A
+            L.append("s_branch .Lend_%=")
+        else:
+            L.append("s_branch .Lcopy_%=")
+
+    rows("f")
+    L.append(".Lslow_%=:")
+    rows("s")
+    L.append(".Lcopy_%=:")
+    for q in range(0, used, 2):
+        L.append(f"s_mov_b64 s[{sa + q}:{sa + q + 1}], s[{sb + q}:{sb + q + 1}]")
+    if weighted:
+        L.append("s_mov_b32 %[wa], %[wb]")
+    L.append("s_branch .Lend_%=")
+    L.append(".Lregion_%=:")
+    for j in range(dpw):
+        nxt = f"s[{tg + 2 * (j + 1)}:{tg + 2 * (j + 1) + 1}]" if j + 1 < dpw else f"s[{ret}:{ret + 1}]"
+        for o in range(noff):
+            for i in range(tp):
+                a = acc0 + j * tp + i
+                if weighted:
+                    L.append(f"v_fmac_f32 v{a}, s{wreg}, v{w0 + o + i}")
+                else:
+                    L.append(f"v_add_f32 v{a}, v{w0 + o + i}, v{a}")
+            L.append(f"s_setpc_b64 {nxt}")
+    L.append(".Lregion_end_%=:")
+    # the host computes block offsets as o * BLK: the assembled region must match
+    L.append(f".if .Lregion_end_%= - .Lregion_%= - {region}")
+    L.append(".error \\\"jump region size differs from the block layout\\\"")
+    L.append(".endif")
+    L.append(".Lend_%=:")
+    asm = "".join(f'    "{ln}\\n\\t"\n' for ln in L)
+    etype = f"ent{ent}_t"
+    outs = ['[t] "=&s"(t)', '[va] "=&v"(va)', '[vrow] "+v"(vrow)', '[toff] "+s"(toff)',
+            f'[ea] "+{{s[{sa}:{sa + ent - 1}]}}"(ea)']
+    if weighted:
+        outs += ['[wa] "+s"(wa)', '[wb] "=&s"(wb)', '[woff] "+s"(woff)']
+    for q in range(nacc // 16):
+        lo = acc0 + 16 * q
+        outs.append(f'[acc{q}] "+{{v[{lo}:{lo + 15}]}}"(acc[{q}])')
+    ins = ['[ncc] "s"(ncc)', '[trs] "s"(trs)', '[rowbytes] "i"(ROWCAP * 4)']
+    if weighted:
+        ins.append('[wrs] "s"(wrs)')
+    clob = [f'"v{w0 + r}"' for r in range(nwin)] + [f'"s{r}"' for r in range(sb, top)] + ['"scc"']
+    wflag = "true" if weighted else "false"
+    return (
+        f"template <int ROWCAP>\n"
+        f"struct JmpPass<{tp}, {dpw}, {nwin}, {cc}, {wflag}, {'true' if full else 'false'}, ROWCAP> {{\n"
+        f"  static __device__ __forceinline__ void run(v16f* acc, uint32_t& vrow, int ncc, {etype}& ea,\n"
+        f"      __amdgpu_buffer_rsrc_t trs, uint32_t& toff, float& wa, __amdgpu_buffer_rsrc_t wrs, uint32_t& woff) {{\n"
+        f"    uint32_t t, va;\n"
+        f"    float wb;\n"
+        f"    (void)wa;\n"
+        f"    (void)wb;\n"
+        f"    (void)wrs;\n"
+        f"    (void)woff;\n"
+        f"    asm volatile(\n{asm}"
+        f"      : {', '.join(outs)}\n"
+        f"      : {', '.join(ins)}\n"
+        f"      : {', '.join(clob)});\n"
+        f"  }}\n"
+        f"}};\n"
+    )
+
+
+# (TP, DPW, NWIN, CC[, first accumulator VGPR]) combinations with a jump-form pass
+JMP_VARIANTS = [
+    (20, 4, 44, 4),
+    (20, 8, 56, 4),
+    (20, 8, 56, 6),
+    (28, 4, 48, 4),
+    (12, 4, 36, 4),
+    (20, 4, 40, 3, 8),
+    (20, 4, 40, 6, 8),
+    (20, 4, 40, 8, 8),
+]
+
+
 # (TP, DPW, NWIN, CC) combinations that get a whole-pass block
 PASS_VARIANTS = [
     (12, 4, 36, 4),
@@ -288,6 +473,32 @@ def main(out_path):
         for weighted in (False, True):
             parts.append(pass_block(tp, dpw, nwin, cc, weighted))
             parts.append("\n")
+    parts += [
+        "// Jump form of a pass (no index mode): same interface as WinPass; the\n",
+        "// table entry's per-row values are block offsets o * JmpBlockBytes<TP>.\n",
+        "template <int TP, int DPW, int NWIN, int CC, bool WEIGHTED, bool FULL, int ROWCAP>\n",
+        "struct JmpPass;\n",
+        "template <int TP, int DPW, int NWIN, int CC>\n",
+        "struct HasJmpPass : std::false_type {};\n",
+        "template <int TP> constexpr int JmpBlockBytes = 4 * TP + 4;\n",
+        "// first accumulator VGPR of a jump-form pass\n",
+        "template <int TP, int DPW, int NWIN, int CC>\n",
+        "struct JmpAcc0 { static constexpr int value = 0; };\n",
+    ]
+    for jv in JMP_VARIANTS:
+        tp, dpw, nwin, cc = jv[:4]
+        acc0 = jv[4] if len(jv) > 4 else ACC0
+        assert jmp_block_bytes(tp) == 4 * tp + 4
+        parts.append(f"template <> struct HasJmpPass<{tp}, {dpw}, {nwin}, {cc}> : std::true_type {{}};\n")
+        parts.append(f"template <> struct JmpAcc0<{tp}, {dpw}, {nwin}, {cc}> {{ static constexpr int value = {acc0}; }};\n")
+    parts.append("\n")
+    for jv in JMP_VARIANTS:
+        tp, dpw, nwin, cc = jv[:4]
+        acc0 = jv[4] if len(jv) > 4 else ACC0
+        for weighted in (False, True):
+            for full in (False, True):
+                parts.append(jmp_pass(tp, dpw, nwin, cc, weighted, full, acc0))
+                parts.append("\n")
     text = "".join(parts)
     if os.path.exists(out_path) and open(out_path).read() == text:
         return

@@ -45,6 +45,9 @@ struct Variant {
   // u8 only: 0 = one LDS copy per row, int32 sums; 1 = four byte-shifted copies, packed sums (at most
   // 256 input rows); 2 = as 1, flushed to int32 sums every 256 rows
   int mode = 0;
+  // f32 only: 1 = each row's DM slots branch into static blocks of adds; the table then holds block byte
+  // offsets o * (4 * tp + 4) in place of the window offsets o
+  int jmp = 0;
   int st() const { return kind == KIND_WIN_F32 ? 64 * tp : 256 * tp; }
   int dt() const { return nwave * dpw; }
   // ints per wave-table entry: f32 {win_start, nl, one offset per row} padded to 4/8/16; u8 packed u16
@@ -63,7 +66,8 @@ const std::vector<int>& default_order(int dir);
 
 // Host-built tile tables for one variant on one delay matrix.
 //   blk[row_tile][rows_in]            {stage_base, stage_len}
-//   wav[wave_tile][rows_in][wav_ints] f32: {win_start, nl, offset of each row...}
+//   wav[wave_tile][rows_in][wav_ints] f32: {win_start, nl, offset of each row...} (jump form: offset times
+//                                      the block size)
 //                                      u8:  {packed u16 offsets...} or {LDS dword offset of each row...}
 struct Tables {
   int variant = -1;

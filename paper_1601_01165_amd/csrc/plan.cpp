@@ -97,12 +97,13 @@ static bool build_tables(const Variant& v, int rows_out, int rows_in, const Dela
               return false;
             }
             maxo = std::max(maxo, o);
-            e[2 + j] = o;
+            e[2 + j] = v.jmp ? o * (4 * v.tp + 4) : o;
           }
           const int nl = std::max(v.tp / 4 + 1, (v.tp + maxo + 3) / 4);
           e[0] = ws;
           e[1] = nl;
-          need = std::max(need, ws + 63 * v.tp + 4 * nl);
+          // full-window variants read all nwin samples of every row
+          need = std::max(need, ws + 63 * v.tp + (v.jmp == 2 ? v.nwin : 4 * nl));
         }
         need = (need + 3) & ~3;
         if (need > v.rowcap) {
@@ -205,9 +206,11 @@ dedisp_status ensure_tables(dedisp_plan p, int dir, int vi, Tables** out) {
 // 1024 DMs.  Variants with wide register windows or int32 sums come last:
 // they fit the widest delay spans and the most channels.
 const std::vector<int>& default_order(int dir) {
-  static const std::vector<int> f32 = {15, 18, 13, 17, 9, 8, 16, 6, 14, 11, 7, 12, 10, 2, 3, 0, 1, 5, 4};
+  static const std::vector<int> f32 = {34, 32, 33, 22, 28, 21, 29, 31, 23, 30, 19, 20, 25, 24, 27, 26, 15, 18, 13,
+                                       17, 9,  8,  16, 6,  14, 11, 7,  12, 10, 2,  3,  0,  1,  5,  4};
   static const std::vector<int> u8 = {16, 20, 15, 21, 12, 13, 17, 14, 18, 6, 2, 0, 5, 19, 9, 3, 4, 1, 8, 7, 10, 11};
-  static const std::vector<int> adj = {9, 8, 6, 11, 12, 7, 10, 13, 18, 15, 17, 16, 14, 2, 3, 1, 0, 5, 4};
+  static const std::vector<int> adj = {26, 27, 32, 34, 33, 19, 21, 29, 20, 30, 9, 8, 6, 11, 12, 7, 10, 13, 22, 28,
+                                       18, 15, 23, 31, 17, 16, 25, 24, 14, 2, 3, 1, 0, 5, 4};
   return dir == 1 ? u8 : dir == 2 ? adj : f32;
 }
 
