@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-cpu-tuned", action="store_true", help="skip the tuned multi-core CPU comparator")
     ap.add_argument("--cpu-tuned-seconds", type=float, default=5.0, help="target time of the tuned CPU run")
     ap.add_argument("--beams", type=int, default=0, help="use only the first N beams (debugging)")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="batched workload: skip the LOFAR-like and differentiable workloads timed after it")
     ap.add_argument("--no-cold", action="store_true",
                     help="skip the cold-cache runs (single-beam workloads: each run after a 512 MB scratch write)")
     return ap.parse_args()
@@ -187,6 +189,59 @@ def cpu_baseline(beam, target_s, search=False):
     }
 
 
+def cpu_baseline_subset(beams, target_s, nsub=16, seed=1704):
+    """Time the plain oracle on a seeded subset of the batched workload's
+    beams: nsub beams drawn without replacement; of each, all channels and
+    samples and a prefix of its DM trials sized so that each beam gets an
+    equal share of what is left of target_s (calibrated on two DM trials per
+    thread of the first beam and scaled by channels x samples; a beam with
+    fewer DM trials than its share leaves the rest to the later ones).  The rate is the subset's
+    DM-trial.samples over the summed time."""
+    import oracle
+    import synth
+
+    oracle.build()
+    idx = sorted(np.random.default_rng(seed).choice(len(beams), size=min(nsub, len(beams)), replace=False).tolist())
+    nth = max(1, oracle.num_threads())
+    per_row = None
+    total_rows_samples = 0
+    total_s = 0.0
+    parts = []
+    for n, i in enumerate(idx):
+        beam = beams[i]
+        delta = oracle.delay_table(beam.freqs(), beam.tsamp_s, beam.dms())
+        x = synth.noise(beam, beam.nsamp + int(delta.max()))
+        if per_row is None:
+            ncal = min(beam.ndm, 2 * nth)
+            oracle.forward_f32(x, delta[:nth], beam.nsamp)  # warm threads and caches
+            t = time.perf_counter()
+            oracle.forward_f32(x, delta[:ncal], beam.nsamp)
+            # seconds per DM trial per (channel x sample), all threads busy
+            per_row = (time.perf_counter() - t) / ncal / (beam.nchan * beam.nsamp)
+        # this beam's share of what is left of the budget
+        nd = int((target_s - total_s) / (len(idx) - n) / (per_row * beam.nchan * beam.nsamp))
+        nd = min(beam.ndm, max(nth, nd - nd % nth))
+        t = time.perf_counter()
+        oracle.forward_f32(x, delta[:nd], beam.nsamp)
+        el = time.perf_counter() - t
+        total_rows_samples += nd * beam.nsamp
+        total_s += el
+        parts.append(f"{beam.nchan}ch/{nd} of {beam.ndm} DMs/{beam.nsamp} samples")
+        if n % 4 == 3:
+            log(f"  cpu baseline: {n + 1} of {len(idx)} beams")
+    return {
+        "value": total_rows_samples / total_s,
+        "unit": "DM-trial·samples/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "host": cpu_model(),
+        "sample": f"{len(idx)} beams of the {len(beams)} drawn with seed {seed} (beam indices {idx}); of each, all "
+                  f"channels and samples and the first DM trials: " + ", ".join(parts) +
+                  f" (Algorithm 1 order, FP32), {total_s:.1f} s",
+        "seconds": total_s,
+    }
+
+
 def cpu_tuned(beam, target_s):
     """Time the tuned multi-core CPU implementation (the paper's CPU
     comparison, Section 5: tiles of DMs x samples, SIMD over samples, threads
@@ -275,26 +330,29 @@ def copy_calibration(args, torch, sync):
                       "kernel_ms": kms, "steps": args.steps, "warmup": args.warmup}), flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: beams are independent and shard by beam "
-                                   "with no exchange; run one process per GPU with a share of the beams"}))
-        sys.exit(2)
+WORKLOAD_TEXT = {
+    "batched": "256 uneven beams in one persistent graph-captured launch (256/512/1024/1536 ch, "
+               "1270-1570 MHz, 512-4096 DMs step 0.25, 8000-20000 samples, 50 us, FP32)",
+    "apertif": "Apertif-like beam: 1024 ch 1270-1570 MHz, 2048 DMs step 0.25, 20000 samples, FP32",
+    "lofar": "LOFAR-like beam: 32 ch 134.875-141.125 MHz, 2048 DMs step 0.01, 200000 samples, u8->i32",
+    "diff": "32 Apertif-like beams, 1024 ch, 1024 DMs, 20000 samples: forward + adjoint + grad_w",
+    "detect_apertif": "Apertif-like beam (as apertif) dedispersed and searched with boxcars of 1..32 "
+                      "samples in one pass, series never stored",
+    "detect_lofar": "LOFAR-like beam (as lofar) dedispersed and searched with boxcars of 1..32 "
+                    "samples in one pass, series never stored",
+}
+
+
+def measure(wl, args, steps, warmup, plain_loop=True):
+    """Prepare workload wl (inputs resident in HBM), tune or pin its kernels,
+    time `steps` steps after `warmup` and return the JSON line as a dict."""
     import torch
 
     import paper_1601_01165_amd as dd
     import synth
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     sync = torch.cuda.synchronize
-
-    wl = args.workload
-    if wl == "copy":
-        copy_calibration(args, torch, sync)
-        return
     extra = {}
     if wl in ("batched", "apertif", "diff", "detect_apertif"):
         k = {"batched": 3, "apertif": 1, "diff": 4, "detect_apertif": 1}[wl]
@@ -319,6 +377,7 @@ def main():
             g.manual_seed(b.seed)
             v = torch.randn(x.shape, generator=g, device=dev)
             x.copy_(torch.clamp(torch.round(128.0 + 16.0 * v), 0, 255).to(torch.uint8))
+            del v
         else:
             fill_noise(x, b.seed)
             delays = None
@@ -347,13 +406,13 @@ def main():
         variant_name = dd.variant_names("f32")[batch.variant]
         log(f"batch created: variant {batch.variant} {variant_name}")
         step = batch.execute
-        if not args.no_plain:
+        if plain_loop and not args.no_plain:
             if not args.no_tune and args.variant is None:
                 for i, (p, b) in enumerate(zip(plans, beams)):
                     p.autotune(1, b.nsamp, "f32")
                     if i % 64 == 63:
                         log(f"  tuned {i + 1} per-beam plans")
-            ms_p, lp, _ = time_steps(batch.execute_per_beam, args.steps, args.warmup, sync)
+            ms_p, lp, _ = time_steps(batch.execute_per_beam, steps, warmup, sync)
             plain = {"value": dm_samples / (ms_p / 1e3), "ms_per_step": ms_p}
             log(f"plain per-beam loop: {ms_p:.3f} ms/step")
         kernel_name = "win_persistent"
@@ -393,8 +452,7 @@ def main():
             log(f"search paths: {extra['detect_tune_ms']}")
             chosen = p.detect_variant(dt)
             p.set_detect_variant(-1, dt)
-            ms_u, _, _ = time_steps(lambda: dd.detect(x, p, nsamp=b.nsamp, workspace=ws), args.steps, args.warmup,
-                                    sync)
+            ms_u, _, _ = time_steps(lambda: dd.detect(x, p, nsamp=b.nsamp, workspace=ws), steps, warmup, sync)
             p.set_detect_variant(chosen, dt)
             extra["unfused_ms_per_step"] = ms_u
             extra["unfused_forward_variant"] = dd.variant_names(dt)[fwd] if fwd >= 0 else "direct"
@@ -438,7 +496,7 @@ def main():
                         f"{dd.variant_names('f32')[av] if av >= 0 else 'direct'} (adjoint)")
 
     log("timing")
-    ms, launch_ms, wall = time_steps(step, args.steps, args.warmup, sync)
+    ms, launch_ms, wall = time_steps(step, steps, warmup, sync)
     value = dm_samples / (ms / 1e3)
     kern_ms = float(np.mean(launch_ms))
     log(f"{ms:.3f} ms/step, {value:.4e} DM-trial*samples/s")
@@ -446,8 +504,8 @@ def main():
     if wl in ("apertif", "lofar", "detect_apertif", "detect_lofar") and not args.no_cold:
         # the inputs of these workloads fit the 256 MB MALL, so the warm steps
         # above may read them from it; these runs start from HBM
-        cold_ms = float(np.median(time_cold(step, max(args.steps, 5), sync)))
-        cold = {"runs": max(args.steps, 5), "ms_median": cold_ms, "value": dm_samples / (cold_ms / 1e3),
+        cold_ms = float(np.median(time_cold(step, max(steps, 5), sync)))
+        cold = {"runs": max(steps, 5), "ms_median": cold_ms, "value": dm_samples / (cold_ms / 1e3),
                 "over_warm": cold_ms / ms,
                 "note": "each run after a 512 MB scratch write (evicts the 256 MB MALL and the L2s), write not timed"}
         log(f"cold: {cold_ms:.3f} ms/step ({cold_ms / ms:.3f}x warm)")
@@ -469,6 +527,8 @@ def main():
         roof.update({"bound": "hbm", "achieved": algo_bytes / (kern_ms / 1e3) / 1e9, "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": algo_bytes / (kern_ms / 1e3) / HBM_PEAK,
                      "note": "algorithmic bytes: input once + int32 output + delay table"})
+        if cold:
+            cold["roofline_frac"] = algo_bytes / (cold_ms / 1e3) / HBM_PEAK
     if wl.startswith("detect_"):
         roof["note"] = ("the paper's dedispersion adds only (one per channel, DM trial and sample); the search's "
                         "own integer/FP32 work is not counted; kernel_ms covers the tile kernel and the record merge")
@@ -481,8 +541,8 @@ def main():
         "value": value,
         "unit": "DM-trial·samples/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
@@ -490,17 +550,7 @@ def main():
         "dtype": "u8" if wl in ("lofar", "detect_lofar") else "f32",
         "data": "synthetic",
         "config": {
-            "workload": {
-                "batched": "256 uneven beams in one persistent graph-captured launch (256/512/1024/1536 ch, "
-                           "1270-1570 MHz, 512-4096 DMs step 0.25, 8000-20000 samples, 50 us, FP32)",
-                "apertif": "Apertif-like beam: 1024 ch 1270-1570 MHz, 2048 DMs step 0.25, 20000 samples, FP32",
-                "lofar": "LOFAR-like beam: 32 ch 134.875-141.125 MHz, 2048 DMs step 0.01, 200000 samples, u8->i32",
-                "diff": "32 Apertif-like beams, 1024 ch, 1024 DMs, 20000 samples: forward + adjoint + grad_w",
-                "detect_apertif": "Apertif-like beam (as apertif) dedispersed and searched with boxcars of 1..32 "
-                                  "samples in one pass, series never stored",
-                "detect_lofar": "LOFAR-like beam (as lofar) dedispersed and searched with boxcars of 1..32 "
-                                "samples in one pass, series never stored",
-            }[wl],
+            "workload": WORKLOAD_TEXT[wl],
             "beams": len(beams),
             "dm_trial_samples_per_step": dm_samples,
             "adds_per_step": adds,
@@ -520,18 +570,60 @@ def main():
         line["plain_value"] = plain["value"]
         line["plain_ms_per_step"] = plain["ms_per_step"]
         line["batched_over_plain"] = value / plain["value"]
+    line.update(extra)
+    return line, beams
+
+
+def secondary(wl, args):
+    """The LOFAR-like (uint8, HBM-bound) and differentiable workloads timed
+    after the headline one, in the same process: their own roofline, variant
+    and kernel time, in a compact object."""
+    import torch
+
+    steps, warmup = {"lofar": (200, 10), "diff": (5, 2)}[wl]
+    line, _ = measure(wl, args, steps, warmup, plain_loop=False)
+    keep = ("value", "unit", "ms_per_step", "steps", "warmup", "dtype", "config", "gbps", "hbm_frac", "valu_frac",
+            "roofline", "cold", "autotune_ms", "adjoint_tune_ms")
+    out = {k: line[k] for k in keep if k in line}
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: beams are independent and shard by beam "
+                                   "with no exchange; run one process per GPU with a share of the beams"}))
+        sys.exit(2)
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(torch.device("cuda:0"))
+    wl = args.workload
+    if wl == "copy":
+        copy_calibration(args, torch, torch.cuda.synchronize)
+        return
+    line, beams = measure(wl, args, args.steps, args.warmup)
     line["paper_context"] = {
         "hd7970_apertif_2000dm": "0.08 s per 1 s of data = 5.0e8 DM-trial*samples/s (AMD HD7970, OpenCL, FP32)"}
-    line.update(extra)
+    if wl == "batched" and not args.no_secondary and not args.beams:
+        # the headline's inputs and outputs (56 GB) are released first
+        import gc
+
+        gc.collect()
+        torch.cuda.empty_cache()
+        line["secondary"] = {w: secondary(w, args) for w in ("lofar", "diff")}
     if not args.no_cpu:
         log("CPU oracle baseline")
-        cb_beam = beams[0]
-        line["cpu_baseline"] = cpu_baseline(cb_beam, args.cpu_seconds, search=wl.startswith("detect_"))
+        if wl == "batched" and not args.beams:
+            line["cpu_baseline"] = cpu_baseline_subset(beams, args.cpu_seconds)
+        else:
+            line["cpu_baseline"] = cpu_baseline(beams[0], args.cpu_seconds, search=wl.startswith("detect_"))
         log(f"cpu baseline {line['cpu_baseline']['value']:.3e}")
     if not args.no_cpu_tuned and not wl.startswith("detect_"):
         log("tuned CPU comparator")
         line["cpu_tuned"] = cpu_tuned(beams[0], args.cpu_tuned_seconds)
-        line["gpu_over_cpu_tuned"] = value / line["cpu_tuned"]["value"]
+        line["gpu_over_cpu_tuned"] = line["value"] / line["cpu_tuned"]["value"]
         log(f"tuned cpu {line['cpu_tuned']['value']:.3e}")
     print(json.dumps(line), flush=True)
 

@@ -12,10 +12,6 @@
 
 #include "internal.h"
 
-namespace dd {
-dedisp_status ensure_tables(dedisp_plan p, int dir, int vi, Tables** out);
-}  // namespace dd
-
 using namespace dd;
 
 struct dedisp_batch_s {
@@ -78,8 +74,17 @@ static dedisp_status check_beam(int i, dedisp_plan p, int32_t ns, const float* i
   return DEDISP_OK;
 }
 
+// Pin (+1) or unpin (-1) the tile tables of variant vi in every beam's plan.
+static void pin_tables(dedisp_batch b, int vi, int by) {
+  for (int i = 0; i < b->nbeam; ++i) {
+    auto it = b->plans[i]->fwd_f32.find(vi);
+    if (it != b->plans[i]->fwd_f32.end()) it->second.pins += by;
+  }
+}
+
 // Free the work table, descriptors and captured graph of the current variant.
 static void drop_work(dedisp_batch b) {
+  if (b->variant >= 0) pin_tables(b, b->variant, -1);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->d_beams) (void)hipFree(b->d_beams);
@@ -175,6 +180,7 @@ static dedisp_status build_work(dedisp_batch b, int vi) {
   if (e != hipSuccess) return hip_fail(e, "querying the device");
   b->grid = ncu * batched_blocks_per_cu(v);
   b->variant = vi;
+  pin_tables(b, vi, +1);  // the descriptors point at these tables
   return DEDISP_OK;
 }
 
@@ -194,52 +200,55 @@ static int tune_batch(dedisp_batch b, float* best_out) {
     (void)hipStreamDestroy(s);
     return -1;
   }
-  int best = -1;
-  float best_ms = 1e30f;
-  for (int vi = 0; vi < (int)vs.size(); ++vi) {
+  const bool weighted = b->d_w[0] != nullptr;
+  // one variant (with nq queues) timed on the batch's buffers, its tables
+  // freed afterwards unless something else holds them; -1 if it does not fit
+  auto time_variant = [&](int vi, int nq, int reps) {
+    float ms = -1.f;
     bool ok = true;
     for (int i = 0; i < b->nbeam && ok; ++i) ok = ensure_tables(b->plans[i], 0, vi, nullptr) == DEDISP_OK;
-    if (!ok) continue;
     drop_work(b);
-    b->nqueue = 1;
-    if (build_work(b, vi) != DEDISP_OK) continue;
-    const bool weighted = b->d_w[0] != nullptr;
-    const float ms = median_ms(
-        [&]() {
-          const hipError_t r = launch_zero_counter(b->d_counter, s);
-          return r == hipSuccess
-                     ? launch_batched(vs[vi], b->d_beams, weighted, b->d_order, b->d_qoff, b->d_counter, b->grid, s)
-                     : r;
-        },
-        s, 2, e0, e1);
-    if (ms > 0 && ms < best_ms) {
-      best_ms = ms;
-      best = vi;
-    }
-  }
-  // the best variant with one queue per XCD as well
-  if (best >= 0) {
-    drop_work(b);
-    b->nqueue = kNumXcd;
-    float ms = -1.f;
-    if (build_work(b, best) == DEDISP_OK) {
-      const bool weighted = b->d_w[0] != nullptr;
+    b->nqueue = nq;
+    if (ok && build_work(b, vi) == DEDISP_OK)
       ms = median_ms(
           [&]() {
             const hipError_t r = launch_zero_counter(b->d_counter, s);
-            return r == hipSuccess ? launch_batched(vs[best], b->d_beams, weighted, b->d_order, b->d_qoff,
-                                                    b->d_counter, b->grid, s)
-                                   : r;
+            return r == hipSuccess
+                       ? launch_batched(vs[vi], b->d_beams, weighted, b->d_order, b->d_qoff, b->d_counter, b->grid, s)
+                       : r;
           },
-          s, 2, e0, e1);
-    }
-    if (!(ms > 0 && ms < best_ms))
-      b->nqueue = 1;
-    else
-      best_ms = ms;
+          s, reps, e0, e1);
+    drop_work(b);
+    for (int i = 0; i < b->nbeam; ++i) drop_spare_tables(b->plans[i], 0, -3);
+    return ms;
+  };
+  // every variant once, then the three fastest again, more carefully
+  std::vector<std::pair<float, int>> first;
+  for (int vi = 0; vi < (int)vs.size(); ++vi) {
+    const float ms = time_variant(vi, 1, 1);
+    if (ms > 0) first.push_back({ms, vi});
   }
+  std::sort(first.begin(), first.end());
+  int best = -1;
+  float best_ms = 1e30f;
+  for (size_t k = 0; k < first.size() && k < 3; ++k) {
+    const float ms = time_variant(first[k].second, 1, 3);
+    if (ms > 0 && ms < best_ms) {
+      best_ms = ms;
+      best = first[k].second;
+    }
+  }
+  // the best variant with one queue per XCD as well
+  int nq = 1;
+  if (best >= 0) {
+    const float ms = time_variant(best, kNumXcd, 3);
+    if (ms > 0 && ms < best_ms) {
+      best_ms = ms;
+      nq = kNumXcd;
+    }
+  }
+  b->nqueue = nq;
   if (best_out) *best_out = best_ms;
-  drop_work(b);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipStreamDestroy(s);
@@ -362,6 +371,8 @@ dedisp_status dedisp_batch_create(dedisp_batch* out, int32_t nbeam, const dedisp
     batch_free(b);
     return fail(DEDISP_E_UNTUNED, "no tiled variant fits every beam of the batch");
   }
+  // tables the search built for other variants
+  for (int i = 0; i < nbeam; ++i) drop_spare_tables(b->plans[i], 0, vi);
   dedisp_status st = build_work(b, vi);
   if (st != DEDISP_OK) {
     batch_free(b);

@@ -77,6 +77,7 @@ struct Tables {
   int32_t* d_blk = nullptr;
   int32_t* d_wav = nullptr;
   size_t bytes = 0;
+  int pins = 0;  // batches whose work table points at these tables (never freed while pinned)
 };
 
 // Single-pulse search (detect_dev.h): boxcar widths 1, 2, ..., 2^(kDetNW - 1);
@@ -170,6 +171,12 @@ hipError_t launch_detect_rows(const void* rows, bool i32, int64_t stride, int nr
 hipError_t launch_det_finish(const DetRec* recs, bool int_vals, int nseries, int ntiles, int nsamp, int nwidth,
                              double* snr, int32_t* width, int32_t* start, double* mean, double* stdv, hipStream_t s);
 int batched_blocks_per_cu(const Variant& v);
+
+// Tile tables of a plan (plan.cpp): build or find (dir 0 forward FP32, 1
+// forward uint8, 2 adjoint); free those of direction dir other than `keep`,
+// the plan's chosen variants and pinned ones.
+dedisp_status ensure_tables(dedisp_plan p, int dir, int vi, Tables** out);
+void drop_spare_tables(dedisp_plan p, int dir, int keep);
 
 // Timing (tune.cpp): ms per launch of fn, the median over `reps` groups of
 // back-to-back launches (about 2 ms per group, one launch for longer ones)

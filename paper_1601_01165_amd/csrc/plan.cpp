@@ -4,8 +4,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <functional>
+#include <thread>
 #include <limits>
 #include <new>
 #include <string>
@@ -62,8 +64,26 @@ static dedisp_status build_delay_table(int nchan, const double* f, double tsamp,
 // v.dpw rows; rows past the end repeat the last row (their results are not
 // stored).
 // ---------------------------------------------------------------------------
-typedef std::function<int(int, int)> DelayFn;
+// Runs f(i) for i in [0, n) on the host's cores (the tables of large plans
+// and batches are built per block row tile, independently).
+template <class F>
+static void parallel_for(int n, F&& f) {
+  const int nt = std::min<int>(n, std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+  if (nt <= 1 || n < 4) {
+    for (int i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<int> next(0);
+  std::vector<std::thread> th;
+  th.reserve(nt);
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&]() {
+      for (int i; (i = next.fetch_add(1)) < n;) f(i);
+    });
+  for (auto& x : th) x.join();
+}
 
+template <class DelayFn>
 static bool build_tables(const Variant& v, int rows_out, int rows_in, const DelayFn& delay, std::vector<int32_t>& blk,
                          std::vector<int32_t>& wav, int& n_row_tiles, int& max_stage, std::string& why) {
   const int DT = v.dt(), DPW = v.dpw, NW = v.nwave, WI = v.wav_ints();
@@ -75,10 +95,12 @@ static bool build_tables(const Variant& v, int rows_out, int rows_in, const Dela
   const int n_wave_tiles = n_row_tiles * NW;
   blk.assign((size_t)n_row_tiles * rows_in * 2, 0);
   wav.assign((size_t)n_wave_tiles * rows_in * WI, 0);
-  max_stage = 0;
-  std::vector<int> d(DT);
-  for (int rt = 0; rt < n_row_tiles; ++rt) {
-    for (int c = 0; c < rows_in; ++c) {
+  std::vector<int> stage_max(n_row_tiles, 0);
+  std::atomic<int> bad(0);  // 1: window span, 2: LDS row, 3: 16-bit offset
+  parallel_for(n_row_tiles, [&](int rt) {
+    std::vector<int> d(DT);
+    int smax = 0;
+    for (int c = 0; c < rows_in && !bad.load(std::memory_order_relaxed); ++c) {
       for (int k = 0; k < DT; ++k) d[k] = delay(std::min(rt * DT + k, rows_out - 1), c);
       if (v.kind == KIND_WIN_F32) {
         const int bmin = *std::min_element(d.begin(), d.end());
@@ -93,8 +115,8 @@ static bool build_tables(const Variant& v, int rows_out, int rows_in, const Dela
           for (int j = 0; j < DPW; ++j) {
             const int o = dw[j] - sbase - ws;
             if (o < 0 || o > v.nwin - v.tp) {
-              why = "delay span within a wave exceeds the register window";
-              return false;
+              bad.store(1);
+              return;
             }
             maxo = std::max(maxo, o);
             e[2 + j] = v.jmp ? o * (4 * v.tp + 4) : o;
@@ -107,12 +129,12 @@ static bool build_tables(const Variant& v, int rows_out, int rows_in, const Dela
         }
         need = (need + 3) & ~3;
         if (need > v.rowcap) {
-          why = "delay span within a block exceeds the LDS row";
-          return false;
+          bad.store(2);
+          return;
         }
         blk[((size_t)rt * rows_in + c) * 2 + 0] = sbase;
         blk[((size_t)rt * rows_in + c) * 2 + 1] = need;
-        max_stage = std::max(max_stage, need);
+        smax = std::max(smax, need);
       } else {
         const int bmin = *std::min_element(d.begin(), d.end());
         const int sbase = bmin & ~15;
@@ -123,8 +145,8 @@ static bool build_tables(const Variant& v, int rows_out, int rows_in, const Dela
           for (int j = 0; j < DPW; ++j) {
             const int o = dw[j] - sbase;
             if (o < 0 || o > 65535) {
-              why = "delay span exceeds the 16-bit offset range";
-              return false;
+              bad.store(3);
+              return;
             }
             if (v.mode == 0) {
               e[j / 2] |= (int32_t)((uint32_t)o << (16 * (j % 2)));
@@ -137,15 +159,24 @@ static bool build_tables(const Variant& v, int rows_out, int rows_in, const Dela
         }
         need = (need + 15) & ~15;
         if (need > v.rowcap) {
-          why = "delay span within a block exceeds the LDS row";
-          return false;
+          bad.store(2);
+          return;
         }
         blk[((size_t)rt * rows_in + c) * 2 + 0] = sbase;
         blk[((size_t)rt * rows_in + c) * 2 + 1] = need;
-        max_stage = std::max(max_stage, need);
+        smax = std::max(smax, need);
       }
     }
+    stage_max[rt] = smax;
+  });
+  switch (bad.load()) {
+    case 1: why = "delay span within a wave exceeds the register window"; return false;
+    case 2: why = "delay span within a block exceeds the LDS row"; return false;
+    case 3: why = "delay span exceeds the 16-bit offset range"; return false;
+    default: break;
   }
+  max_stage = 0;
+  for (int m : stage_max) max_stage = std::max(max_stage, m);
   return true;
 }
 
@@ -153,6 +184,21 @@ static void free_tables(Tables& t) {
   if (t.d_blk) (void)hipFree(t.d_blk);
   if (t.d_wav) (void)hipFree(t.d_wav);
   t = Tables();
+}
+
+void drop_spare_tables(dedisp_plan p, int dir, int keep) {
+  std::map<int, Tables>& m = dir == 0 ? p->fwd_f32 : dir == 1 ? p->fwd_u8 : p->adj_f32;
+  for (auto it = m.begin(); it != m.end();) {
+    const int vi = it->first;
+    const bool chosen = vi == keep || (dir == 0 && (vi == p->var_f32 || vi == p->var_det_f32)) ||
+                        (dir == 1 && (vi == p->var_u8 || vi == p->var_det_u8)) || (dir == 2 && vi == p->var_adj);
+    if (chosen || it->second.pins > 0) {
+      ++it;
+      continue;
+    }
+    free_tables(it->second);
+    it = m.erase(it);
+  }
 }
 
 // Build and upload the tables of variant `vi` in direction `dir`

@@ -17,7 +17,6 @@
 #include "internal.h"
 
 namespace dd {
-dedisp_status ensure_tables(dedisp_plan p, int dir, int vi, Tables** out);
 
 // FNV-1a over the delay table: two plans with equal tables share tuning.
 uint64_t delay_table_hash(dedisp_plan p) {
@@ -181,17 +180,33 @@ dedisp_status dedisp_autotune(dedisp_plan p, int32_t nbeam, int32_t nsamp, dedis
   std::vector<float>& times = last_times(p, t);
   times.assign(vs.size() + 1, -1.f);
   const int saved = u8 ? p->var_u8 : p->var_f32;
-  int best = -2;
-  float best_ms = 1e30f;
-  for (int vi = -1; vi < (int)vs.size(); ++vi) {
-    if (dedisp_plan_set_variant(p, t, vi) != DEDISP_OK) continue;
-    float ms = median_ms(
+  const int dir = u8 ? 1 : 0;
+  auto time_variant = [&](int vi, int reps) {
+    if (dedisp_plan_set_variant(p, t, vi) != DEDISP_OK) return -1.f;
+    return median_ms(
         [&]() {
           return dedisp_execute(p, nbeam, nsamp, d_in, t, in_stride, nullptr, d_out, out_t, out_stride, s) == DEDISP_OK
                      ? hipSuccess
                      : hipErrorUnknown;
         },
-        s, 3, e0, e1);
+        s, reps, e0, e1);
+  };
+  // every variant once (its tables freed again), then the three fastest
+  // more carefully
+  std::vector<std::pair<float, int>> first;
+  for (int vi = -1; vi < (int)vs.size(); ++vi) {
+    const float ms = time_variant(vi, 1);
+    times[vi < 0 ? vs.size() : (size_t)vi] = ms;
+    if (ms > 0) first.push_back({ms, vi});
+    (u8 ? p->var_u8 : p->var_f32) = saved;
+    drop_spare_tables(p, dir, -3);
+  }
+  std::sort(first.begin(), first.end());
+  int best = -2;
+  float best_ms = 1e30f;
+  for (size_t k = 0; k < first.size() && k < 3; ++k) {
+    const int vi = first[k].second;
+    const float ms = time_variant(vi, 3);
     times[vi < 0 ? vs.size() : (size_t)vi] = ms;
     if (ms > 0 && ms < best_ms) {
       best_ms = ms;
@@ -209,6 +224,7 @@ dedisp_status dedisp_autotune(dedisp_plan p, int32_t nbeam, int32_t nsamp, dedis
   }
   dedisp_status st = dedisp_plan_set_variant(p, t, best);
   if (st != DEDISP_OK) return st;
+  drop_spare_tables(p, dir, best);
   tune_cache_store(cache_path, key, best < 0 ? "direct" : vs[best].name, best_ms);
   return DEDISP_OK;
 }
@@ -246,18 +262,31 @@ dedisp_status dedisp_autotune_adjoint(dedisp_plan p, int32_t nbeam, int32_t nsam
   (void)hipEventCreate(&e1);
   const int saved = p->var_adj;
   std::vector<float> times(vs.size() + 1, -1.f);
-  int best = -2;
-  float best_ms = 1e30f;
-  for (int vi = -1; vi < (int)vs.size(); ++vi) {
-    if (dedisp_plan_set_adjoint_variant(p, vi) != DEDISP_OK) continue;
-    const float t = median_ms(
+  auto time_variant = [&](int vi, int reps) {
+    if (dedisp_plan_set_adjoint_variant(p, vi) != DEDISP_OK) return -1.f;
+    return median_ms(
         [&]() {
           return dedisp_adjoint(p, nbeam, nsamp, (int32_t)nin, d_g, gs, nullptr, d_x, nin, d_gi, nin, d_gw, d_ws,
                                 ws_bytes, s) == DEDISP_OK
                      ? hipSuccess
                      : hipErrorUnknown;
         },
-        s, 3, e0, e1);
+        s, reps, e0, e1);
+  };
+  std::vector<std::pair<float, int>> first;
+  for (int vi = -1; vi < (int)vs.size(); ++vi) {
+    const float t = time_variant(vi, 1);
+    times[vi < 0 ? vs.size() : (size_t)vi] = t;
+    if (t > 0) first.push_back({t, vi});
+    p->var_adj = saved;
+    drop_spare_tables(p, 2, -3);
+  }
+  std::sort(first.begin(), first.end());
+  int best = -2;
+  float best_ms = 1e30f;
+  for (size_t k = 0; k < first.size() && k < 3; ++k) {
+    const int vi = first[k].second;
+    const float t = time_variant(vi, 3);
     times[vi < 0 ? vs.size() : (size_t)vi] = t;
     if (t > 0 && t < best_ms) {
       best_ms = t;
@@ -274,7 +303,9 @@ dedisp_status dedisp_autotune_adjoint(dedisp_plan p, int32_t nbeam, int32_t nsam
     (void)dedisp_plan_set_adjoint_variant(p, saved);
     return fail(DEDISP_E_UNTUNED, "no adjoint variant ran");
   }
-  return dedisp_plan_set_adjoint_variant(p, best);
+  const dedisp_status st = dedisp_plan_set_adjoint_variant(p, best);
+  if (st == DEDISP_OK) drop_spare_tables(p, 2, best);
+  return st;
 }
 
 int32_t dedisp_autotune_times(dedisp_plan p, dedisp_dtype t, float* ms, int32_t n) {
