@@ -153,6 +153,34 @@ dedisp_status dedisp_adjoint(dedisp_plan plan, int32_t nbeam, int32_t nsamp, int
 /* Bytes of workspace dedisp_adjoint needs for the weight gradient. */
 size_t dedisp_adjoint_workspace_bytes(dedisp_plan plan, int32_t nbeam, int32_t nin);
 
+/* Allocation-free form of dedisp_adjoint, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments and results as dedisp_adjoint (the
+ * same kernels, so grad_in and grad_w are bit-identical to it) without the
+ * workspace: the weight gradient's FP64 partial sums go to a fixed scratch
+ * array of DEDISP_ADJOINT_NOALLOC_SCRATCH_BYTES (8 MiB) that the library
+ * holds on every GPU it runs on until the process ends.  Nothing is
+ * allocated or freed by the call: the plan's adjoint kernel and its tile
+ * tables must exist already (dedisp_plan_prepare(plan, ..., 1), or an
+ * earlier dedisp_adjoint call).  Every call writes each partial sum it later
+ * reads, so the scratch needs no clearing, but calls on one GPU share the
+ * array: calls that overlap (on different streams, or in different threads)
+ * race and give wrong weight gradients.  Calls without d_grad_w do not touch
+ * the scratch.
+ * Errors as for dedisp_adjoint, plus DEDISP_E_WORKSPACE when the partial sums
+ * (dedisp_adjoint_noalloc_bytes) exceed the scratch (use dedisp_adjoint
+ * then), DEDISP_E_INVALID when the adjoint kernel or its tables are not
+ * prepared or the current device is not the plan's. */
+#define DEDISP_ADJOINT_NOALLOC_SCRATCH_BYTES ((size_t)8 << 20)
+dedisp_status dedisp_adjoint_noalloc(dedisp_plan plan, int32_t nbeam, int32_t nsamp, int32_t nin, const float* d_g,
+                                     int64_t g_stride, const float* d_w, const float* d_in, int64_t in_stride,
+                                     float* d_grad_in, int64_t gi_stride, float* d_grad_w, void* stream);
+
+/* Scratch bytes dedisp_adjoint_noalloc needs for the weight gradient with
+ * the plan's chosen adjoint kernel (nbeam x time parts x nchan FP64 values);
+ * 0 if that kernel is not chosen yet. */
+size_t dedisp_adjoint_noalloc_bytes(dedisp_plan plan, int32_t nbeam, int32_t nin);
+
 /* ------------------------------------------------------------------------ */
 /* Batched execution of many uneven beams (multi-beam use, Section 5.1)      */
 /* ------------------------------------------------------------------------ */

@@ -27,7 +27,7 @@ from ._clib import F32, I32, U8, DedispError, check
 
 __all__ = [
     "Plan", "Batch", "DedispFunction", "DedispError", "compute_delays", "dedisperse", "dedisperse_autograd",
-    "adjoint", "empty_rows", "variant_names", "lib", "detect", "detect_rows",
+    "adjoint", "adjoint_noalloc", "empty_rows", "variant_names", "lib", "detect", "detect_rows",
 ]
 
 
@@ -257,6 +257,40 @@ def adjoint(g: torch.Tensor, plan: Plan, nin: int, w: torch.Tensor | None = None
                                ctypes.c_void_p(ws.data_ptr()) if ws is not None else None, nbytes,
                                _stream(gr.device)), "adjoint")
     return gi, gw
+
+
+def adjoint_noalloc(g: torch.Tensor, plan: Plan, nin: int, w: torch.Tensor | None = None,
+                    x: torch.Tensor | None = None, grad_in: torch.Tensor | None = None,
+                    grad_w: torch.Tensor | None = None):
+    """adjoint() through the allocation-free entry point: the caller passes
+    the outputs (grad_in [nbeam][nchan][nin] with 16-byte rows, grad_w [nchan]
+    float32, either may be None) and nothing is allocated, by this function or
+    the library; the plan's adjoint kernel must be prepared.  Returns
+    (grad_in, grad_w)."""
+    if not _rows_ok(g) or g.dtype != torch.float32:
+        raise ValueError("g must be float32 [nbeam][ndm][nsamp] with 16-byte aligned rows")
+    nb, nd, ns = g.shape
+    if nd != plan.ndm:
+        raise ValueError(f"gradient has {nd} DM rows, plan has {plan.ndm}")
+    if x is not None and (not _rows_ok(x) or x.dtype != torch.float32 or tuple(x.shape[:2]) != (nb, plan.nchan)):
+        raise ValueError("x must be float32 [nbeam][nchan][>= nin] with 16-byte aligned rows")
+    if grad_in is not None and (not _rows_ok(grad_in) or grad_in.dtype != torch.float32
+                                or tuple(grad_in.shape) != (nb, plan.nchan, nin)):
+        raise ValueError("grad_in must be float32 [nbeam][nchan][nin] with 16-byte aligned rows")
+    if grad_w is not None and (grad_w.dtype != torch.float32 or grad_w.numel() != plan.nchan
+                               or not grad_w.is_contiguous()):
+        raise ValueError("grad_w must be a contiguous float32 tensor of nchan values")
+    if w is not None and (w.dtype != torch.float32 or w.numel() != plan.nchan or not w.is_contiguous()):
+        raise ValueError("w must be a contiguous float32 tensor of nchan values")
+    check(lib().dedisp_adjoint_noalloc(plan.handle, nb, ns, nin, ctypes.c_void_p(g.data_ptr()), g.stride(1),
+                                       ctypes.c_void_p(w.data_ptr()) if w is not None else None,
+                                       ctypes.c_void_p(x.data_ptr()) if x is not None else None,
+                                       x.stride(1) if x is not None else 0,
+                                       ctypes.c_void_p(grad_in.data_ptr()) if grad_in is not None else None,
+                                       grad_in.stride(1) if grad_in is not None else 0,
+                                       ctypes.c_void_p(grad_w.data_ptr()) if grad_w is not None else None,
+                                       _stream(g.device)), "adjoint_noalloc")
+    return grad_in, grad_w
 
 
 def _ptr(t):

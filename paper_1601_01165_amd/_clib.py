@@ -29,6 +29,8 @@ SIGNATURES = {
     "dedisp_execute": (i32, [vp, i32, i32, vp, i32, i64, vp, vp, i32, i64, vp]),
     "dedisp_adjoint": (i32, [vp, i32, i32, i32, vp, i64, vp, vp, i64, vp, i64, vp, vp, sz, vp]),
     "dedisp_adjoint_workspace_bytes": (sz, [vp, i32, i32]),
+    "dedisp_adjoint_noalloc": (i32, [vp, i32, i32, i32, vp, i64, vp, vp, i64, vp, i64, vp, vp]),
+    "dedisp_adjoint_noalloc_bytes": (sz, [vp, i32, i32]),
     "dedisp_batch_create": (i32, [ctypes.POINTER(vp), i32, vp, vp, vp, i32, vp, vp, vp, vp, i32, cp]),
     "dedisp_batch_cache_hit": (i32, [vp]),
     "dedisp_execute_batched": (i32, [vp, vp]),

@@ -7,6 +7,8 @@
 #include <atomic>
 #include <cstdio>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <thread>
 #include <limits>
 #include <new>
@@ -277,6 +279,121 @@ static void ensure_chosen(dedisp_plan p, int dir) {
   if (v == -2) v = default_variant(p, dir);
 }
 
+// Scratch of the allocation-free adjoint (dedisp_adjoint_noalloc): the
+// per-tile FP64 partial sums of the weight gradient.  Every GPU the library
+// runs on holds its own copy until the process ends.  Host code never uses
+// the array's name as an address: the device address of the current
+// device's copy comes from scratch_address().
+constexpr size_t kNoAllocScratchBytes = DEDISP_ADJOINT_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+// Device address of the current device's scratch, looked up once per device
+// (at plan creation, with that device current); nullptr with the error set
+// if the lookup fails.
+static void* scratch_address(int device) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(device);
+  if (it != addr.end()) return it->second;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hip_fail(e == hipSuccess ? hipErrorInvalidSymbol : e, "looking up the adjoint scratch array");
+    return nullptr;
+  }
+  addr[device] = ptr;
+  return ptr;
+}
+
+// The adjoint's launches with the partial-sum buffer given (null when no
+// weight gradient is asked for).  With may_allocate false the plan's chosen
+// adjoint variant and its tables must exist already (nothing is built).
+static dedisp_status adjoint_impl(dedisp_plan p, int32_t nbeam, int32_t nsamp, int32_t nin, const float* d_g,
+                                  int64_t g_stride, const float* d_w, const float* d_in, int64_t in_stride,
+                                  float* d_grad_in, int64_t gi_stride, float* d_grad_w, double* partial,
+                                  hipStream_t s, bool may_allocate) {
+  hipError_t e;
+  int nparts;
+  if (may_allocate) {
+    ensure_chosen(p, 2);
+  } else if (p->var_adj == -2) {
+    return fail(DEDISP_E_INVALID, "the adjoint kernel is not chosen yet: call dedisp_plan_prepare first");
+  }
+  const int vi = p->var_adj;
+  if (vi < 0) {
+    e = launch_direct_adjoint(d_g, g_stride, g_stride * p->ndm, p->d_delay, p->nchan, p->ndm, nsamp, nin, d_w,
+                              d_grad_in, gi_stride, gi_stride * p->nchan, d_in, in_stride, in_stride * p->nchan,
+                              partial, nbeam, s);
+    if (e != hipSuccess) return hip_fail(e, "launching the direct adjoint kernel");
+    nparts = nbeam * ((nin + 255) / 256);
+  } else {
+    Tables* t = nullptr;
+    if (may_allocate) {
+      dedisp_status st = ensure_tables(p, 2, vi, &t);
+      if (st != DEDISP_OK) return st;
+    } else {
+      auto it = p->adj_f32.find(vi);
+      if (it == p->adj_f32.end())
+        return fail(DEDISP_E_INVALID, "the adjoint tile tables are not built: call dedisp_plan_prepare first");
+      t = &it->second;
+    }
+    const Variant& v = variants_f32()[vi];
+    TileArgs a = {};
+    a.in = d_g;
+    a.in_stride = g_stride;
+    a.in_beam_stride = g_stride * p->ndm;
+    a.in_shift = -p->adj_pad;
+    a.in_lo = p->adj_pad;
+    a.in_hi = p->adj_pad + nsamp;
+    a.rows_in = p->ndm;
+    a.rows_out = p->nchan;
+    a.nout = nin;
+    a.n_time_tiles = (nin + v.st() - 1) / v.st();
+    a.n_row_tiles = t->n_row_tiles;
+    a.blk = t->d_blk;
+    a.wav = t->d_wav;
+    a.w_in = nullptr;
+    a.out = d_grad_in;
+    a.out_stride = gi_stride;
+    a.out_beam_stride = gi_stride * p->nchan;
+    a.w_out = d_w;
+    a.x = d_in;
+    a.x_stride = in_stride;
+    a.x_beam_stride = in_stride * p->nchan;
+    a.partial = partial;
+    e = launch_tiled(v, a, nbeam, true, s);
+    if (e != hipSuccess) return hip_fail(e, "launching the tiled adjoint kernel");
+    nparts = nbeam * a.n_time_tiles;
+  }
+  if (d_grad_w) {
+    e = launch_reduce_gradw(partial, nparts, p->nchan, d_grad_w, s);
+    if (e != hipSuccess) return hip_fail(e, "launching the grad_w reduction");
+  }
+  return DEDISP_OK;
+}
+
+// Argument checks shared by both adjoint entry points.
+static dedisp_status adjoint_check(dedisp_plan p, int32_t nbeam, int32_t nsamp, int32_t nin, const float* d_g,
+                                   int64_t g_stride, const float* d_w, const float* d_in, int64_t in_stride,
+                                   float* d_grad_in, int64_t gi_stride, float* d_grad_w) {
+  if (!p) return fail(DEDISP_E_INVALID, "plan is NULL");
+  if (nbeam < 1 || nsamp < 1 || nin < 1) return fail(DEDISP_E_INVALID, "nbeam, nsamp and nin must be >= 1");
+  if (nbeam > kMaxBeams) return fail(DEDISP_E_SHAPE, "at most 65535 beams per call");
+  if (!d_g) return fail(DEDISP_E_INVALID, "output gradient is NULL");
+  if (d_grad_w && !d_in) return fail(DEDISP_E_INVALID, "grad_w needs the forward input");
+  if (g_stride < nsamp) return fail(DEDISP_E_SHAPE, "g_stride < nsamp");
+  if (d_grad_in && gi_stride < nin) return fail(DEDISP_E_SHAPE, "gi_stride < nin");
+  if (d_in && in_stride < nin) return fail(DEDISP_E_SHAPE, "in_stride < nin");
+  if ((int64_t)nsamp + p->max_delay > nin) return fail(DEDISP_E_SHAPE, "nin < nsamp + max_delay");
+  if (nin > kMaxRow || g_stride > kMaxRow || (d_in && in_stride > kMaxRow) || (d_grad_in && gi_stride > kMaxRow))
+    return fail(DEDISP_E_SHAPE, "rows longer than 2^29 samples are not supported");
+  if (!aligned16(d_g) || (g_stride * 4) % 16 || (d_grad_in && (!aligned16(d_grad_in) || (gi_stride * 4) % 16)) ||
+      (d_in && (!aligned16(d_in) || (in_stride * 4) % 16)) || (d_w && ((uintptr_t)d_w & 3)))
+    return fail(DEDISP_E_ALIGN, "pointers and row byte sizes must be multiples of 16 bytes");
+  return DEDISP_OK;
+}
+
 }  // namespace dd
 
 using namespace dd;
@@ -328,6 +445,12 @@ dedisp_status dedisp_plan_create(dedisp_plan* plan, int32_t nchan, const double*
     e = hipMemcpy(p->d_delay, p->delay.data(), p->delay.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     st = hip_fail(e, "uploading the delay table");
+    dedisp_plan_destroy(p);
+    return st;
+  }
+  // the allocation-free adjoint's scratch on this device, looked up once
+  if (!scratch_address(p->device)) {
+    st = DEDISP_E_HIP;
     dedisp_plan_destroy(p);
     return st;
   }
@@ -504,75 +627,53 @@ dedisp_status dedisp_adjoint(dedisp_plan p, int32_t nbeam, int32_t nsamp, int32_
                              int64_t g_stride, const float* d_w, const float* d_in, int64_t in_stride,
                              float* d_grad_in, int64_t gi_stride, float* d_grad_w, void* d_ws, size_t ws_bytes,
                              void* stream) {
-  if (!p) return fail(DEDISP_E_INVALID, "plan is NULL");
-  if (nbeam < 1 || nsamp < 1 || nin < 1) return fail(DEDISP_E_INVALID, "nbeam, nsamp and nin must be >= 1");
-  if (nbeam > kMaxBeams) return fail(DEDISP_E_SHAPE, "at most 65535 beams per call");
-  if (!d_g) return fail(DEDISP_E_INVALID, "output gradient is NULL");
+  dedisp_status st =
+      adjoint_check(p, nbeam, nsamp, nin, d_g, g_stride, d_w, d_in, in_stride, d_grad_in, gi_stride, d_grad_w);
+  if (st != DEDISP_OK) return st;
   if (!d_grad_in && !d_grad_w) return DEDISP_OK;
-  if (d_grad_w && !d_in) return fail(DEDISP_E_INVALID, "grad_w needs the forward input");
-  if (g_stride < nsamp) return fail(DEDISP_E_SHAPE, "g_stride < nsamp");
-  if (d_grad_in && gi_stride < nin) return fail(DEDISP_E_SHAPE, "gi_stride < nin");
-  if (d_in && in_stride < nin) return fail(DEDISP_E_SHAPE, "in_stride < nin");
-  if ((int64_t)nsamp + p->max_delay > nin) return fail(DEDISP_E_SHAPE, "nin < nsamp + max_delay");
-  if (nin > kMaxRow || g_stride > kMaxRow || (d_in && in_stride > kMaxRow) || (d_grad_in && gi_stride > kMaxRow))
-    return fail(DEDISP_E_SHAPE, "rows longer than 2^29 samples are not supported");
-  if (!aligned16(d_g) || (g_stride * 4) % 16 || (d_grad_in && (!aligned16(d_grad_in) || (gi_stride * 4) % 16)) ||
-      (d_in && (!aligned16(d_in) || (in_stride * 4) % 16)) || (d_w && ((uintptr_t)d_w & 3)))
-    return fail(DEDISP_E_ALIGN, "pointers and row byte sizes must be multiples of 16 bytes");
   if (d_grad_w) {
     if (!d_ws) return fail(DEDISP_E_WORKSPACE, "workspace is NULL");
     if (ws_bytes < dedisp_adjoint_workspace_bytes(p, nbeam, nin)) return fail(DEDISP_E_WORKSPACE, "workspace too small");
     if ((uintptr_t)d_ws & 7) return fail(DEDISP_E_ALIGN, "workspace must be 8-byte aligned");
   }
-  hipStream_t s = (hipStream_t)stream;
-  double* partial = d_grad_w ? (double*)d_ws : nullptr;
-  hipError_t e;
-  int nparts;
-  ensure_chosen(p, 2);
+  return adjoint_impl(p, nbeam, nsamp, nin, d_g, g_stride, d_w, d_in, in_stride, d_grad_in, gi_stride, d_grad_w,
+                      d_grad_w ? (double*)d_ws : nullptr, (hipStream_t)stream, true);
+}
+
+size_t dedisp_adjoint_noalloc_bytes(dedisp_plan p, int32_t nbeam, int32_t nin) {
+  if (!p || nbeam < 1 || nin < 1 || p->var_adj == -2) return 0;
   const int vi = p->var_adj;
-  if (vi < 0) {
-    e = launch_direct_adjoint(d_g, g_stride, g_stride * p->ndm, p->d_delay, p->nchan, p->ndm, nsamp, nin, d_w,
-                              d_grad_in, gi_stride, gi_stride * p->nchan, d_in, in_stride, in_stride * p->nchan,
-                              partial, nbeam, s);
-    if (e != hipSuccess) return hip_fail(e, "launching the direct adjoint kernel");
-    nparts = nbeam * ((nin + 255) / 256);
-  } else {
-    Tables* t = nullptr;
-    dedisp_status st = ensure_tables(p, 2, vi, &t);
-    if (st != DEDISP_OK) return st;
-    const Variant& v = variants_f32()[vi];
-    TileArgs a = {};
-    a.in = d_g;
-    a.in_stride = g_stride;
-    a.in_beam_stride = g_stride * p->ndm;
-    a.in_shift = -p->adj_pad;
-    a.in_lo = p->adj_pad;
-    a.in_hi = p->adj_pad + nsamp;
-    a.rows_in = p->ndm;
-    a.rows_out = p->nchan;
-    a.nout = nin;
-    a.n_time_tiles = (nin + v.st() - 1) / v.st();
-    a.n_row_tiles = t->n_row_tiles;
-    a.blk = t->d_blk;
-    a.wav = t->d_wav;
-    a.w_in = nullptr;
-    a.out = d_grad_in;
-    a.out_stride = gi_stride;
-    a.out_beam_stride = gi_stride * p->nchan;
-    a.w_out = d_w;
-    a.x = d_in;
-    a.x_stride = in_stride;
-    a.x_beam_stride = in_stride * p->nchan;
-    a.partial = partial;
-    e = launch_tiled(v, a, nbeam, true, s);
-    if (e != hipSuccess) return hip_fail(e, "launching the tiled adjoint kernel");
-    nparts = nbeam * a.n_time_tiles;
-  }
+  // one FP64 partial sum per channel and (beam, time part): 256-sample parts
+  // for the direct kernel, the variant's time tiles otherwise
+  const int64_t part = vi < 0 ? 256 : variants_f32()[vi].st();
+  return (size_t)nbeam * (size_t)((nin + part - 1) / part) * (size_t)p->nchan * sizeof(double);
+}
+
+dedisp_status dedisp_adjoint_noalloc(dedisp_plan p, int32_t nbeam, int32_t nsamp, int32_t nin, const float* d_g,
+                                     int64_t g_stride, const float* d_w, const float* d_in, int64_t in_stride,
+                                     float* d_grad_in, int64_t gi_stride, float* d_grad_w, void* stream) {
+  dedisp_status st =
+      adjoint_check(p, nbeam, nsamp, nin, d_g, g_stride, d_w, d_in, in_stride, d_grad_in, gi_stride, d_grad_w);
+  if (st != DEDISP_OK) return st;
+  if (!d_grad_in && !d_grad_w) return DEDISP_OK;
+  if (p->var_adj == -2)
+    return fail(DEDISP_E_INVALID, "the adjoint kernel is not chosen yet: call dedisp_plan_prepare first");
+  double* partial = nullptr;
   if (d_grad_w) {
-    e = launch_reduce_gradw(partial, nparts, p->nchan, d_grad_w, s);
-    if (e != hipSuccess) return hip_fail(e, "launching the grad_w reduction");
+    const size_t need = dedisp_adjoint_noalloc_bytes(p, nbeam, nin);
+    if (need > kNoAllocScratchBytes)
+      return fail(DEDISP_E_WORKSPACE, "the weight gradient's partial sums (" + std::to_string(need) +
+                                          " bytes) exceed the fixed scratch of " +
+                                          std::to_string(kNoAllocScratchBytes) + " bytes; use dedisp_adjoint");
+    int dev = 0;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "querying the current device");
+    if (dev != p->device) return fail(DEDISP_E_INVALID, "the plan belongs to another device");
+    partial = static_cast<double*>(scratch_address(dev));
+    if (!partial) return DEDISP_E_HIP;
   }
-  return DEDISP_OK;
+  return adjoint_impl(p, nbeam, nsamp, nin, d_g, g_stride, d_w, d_in, in_stride, d_grad_in, gi_stride, d_grad_w,
+                      partial, (hipStream_t)stream, false);
 }
 
 }  // extern "C"
