@@ -7,7 +7,7 @@
  * The sum is the one of Algorithm 1 (Section 2.1): for every beam b, DM
  * trial j and output sample t,
  *     out[b][j][t] = sum over channels c, ascending, of w[c] * in[b][c][t + delta[j][c]]
- * with one rounding per term (fmaf when w is given, a plain add otherwise),
+ * with the weighted sample w[c] * x rounded, then added with one rounding (a plain add when w is NULL),
  * so FP32 results equal a sequential loop bit for bit; uint8 input sums into
  * int32 exactly.
  *

@@ -92,9 +92,10 @@ int oracle_delay_table(int nchan, const double* freq_mhz, double tsamp_s, int nd
 /* Forward dedispersion, Section 2.1 Algorithm 1.                            */
 /*   out[b][dm][sample] = sum over chan ascending of                         */
 /*                        w[chan] * in[b][chan][sample + delta[dm][chan]]    */
-/* The weight w is an extension (absent from Algorithm 1); w == NULL means   */
-/* every weight is 1.  Each term is added with one rounding (fused           */
-/* multiply-add); with w = 1 that is the plain FP32 add of Algorithm 1.      */
+/* The weight w is an extension (absent from Algorithm 1): a per-channel    */
+/* gain applied to the data before dedispersion, so each term is the FP32    */
+/* product w * x (rounded), then added to the FP32 sum (rounded); w == NULL  */
+/* means every weight is 1, i.e. the plain FP32 adds of Algorithm 1.         */
 /* Layouts: in [nbeam][nchan][in_stride], out [nbeam][ndm][out_stride].      */
 /* The caller guarantees in_stride >= nsamp + max delta.                     */
 /* ------------------------------------------------------------------------ */
@@ -111,7 +112,10 @@ void oracle_forward_f32(int nbeam, int nchan, int ndm, int nsamp, const float* i
         const float* src = in + ((size_t)b * nchan + c) * in_stride + delta[(size_t)j * nchan + c];
         if (w) {
           const float wc = w[c];
-          for (int t = 0; t < nsamp; ++t) row[t] = fmaf(wc, src[t], row[t]);
+          for (int t = 0; t < nsamp; ++t) {
+            const float term = wc * src[t]; /* the weighted sample, rounded */
+            row[t] = row[t] + term;
+          }
         } else {
           for (int t = 0; t < nsamp; ++t) row[t] = row[t] + src[t];
         }
@@ -164,8 +168,8 @@ void oracle_forward_u8(int nbeam, int nchan, int ndm, int nsamp, const uint8_t* 
 
 /* Selected outputs, one by one, for checks at sizes where the full output is
  * too costly on the CPU.  Point p is (beam[p], dm[p], sample[p]).  Writes the
- * FP32 sum (channels ascending, one rounding per term) and the FP64 error
- * scale sum |w * x|. */
+ * FP32 sum (channels ascending, each weighted sample rounded, then each add
+ * rounded) and the FP64 error scale sum |w * x|. */
 void oracle_forward_points_f32(int nchan, const float* in, int64_t in_stride, int64_t beam_stride,
                                const int32_t* delta, const float* w, int64_t npts, const int32_t* pb,
                                const int32_t* pdm, const int32_t* ps, float* out, double* absout) {
@@ -178,7 +182,8 @@ void oracle_forward_points_f32(int nchan, const float* in, int64_t in_stride, in
     for (int chan = 0; chan < nchan; ++chan) {
       float x = inb[(size_t)chan * in_stride + ps[p] + drow[chan]];
       if (w) {
-        acc = fmaf(w[chan], x, acc);
+        const float term = w[chan] * x;
+        acc = acc + term;
         a += fabs((double)w[chan] * (double)x);
       } else {
         acc = acc + x;

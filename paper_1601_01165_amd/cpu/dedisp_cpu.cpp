@@ -54,7 +54,7 @@ static inline void tile(const TI* in, int64_t is, const int32_t* delta, int ncha
 #pragma omp simd
         for (int t = 0; t < TT; ++t) {
           if (WEIGHTED)
-            acc[d][t] = std::fma(wc, (TA)src[t], acc[d][t]);
+            acc[d][t] = acc[d][t] + wc * (TA)src[t];
           else
             acc[d][t] = acc[d][t] + (TA)src[t];
         }
@@ -68,7 +68,7 @@ static inline void tile(const TI* in, int64_t is, const int32_t* delta, int ncha
         const TI* src = row + drow[d][c];
         for (int t = 0; t < nt; ++t) {
           if (WEIGHTED)
-            acc[d][t] = std::fma(wc, (TA)src[t], acc[d][t]);
+            acc[d][t] = acc[d][t] + wc * (TA)src[t];
           else
             acc[d][t] = acc[d][t] + (TA)src[t];
         }

@@ -176,37 +176,65 @@ def test_forward_fp32_within_summation_bound():
     w = (1.0 + 0.1 * rng.standard_normal(nc)).astype(np.float32)
     o32 = oracle.forward_f32(x, delta, ns, w).astype(np.float64)
     o64, scale = oracle.forward_f64(x.astype(np.float64), delta, ns, w.astype(np.float64), with_scale=True)
-    # sequential FP32 fused sum: |err| <= nc * u * sum |w x| (u = 2^-24)
-    assert (np.abs(o32 - o64) <= nc * 2.0 ** -24 * scale).all()
+    # sequential FP32 sum of rounded products: |err| <= (nc + 1) * u * sum |w x| (u = 2^-24)
+    assert (np.abs(o32 - o64) <= (nc + 1) * 2.0 ** -24 * scale).all()
     assert np.abs(o32 - o64).max() > 0  # FP32 really is FP32
 
 
 @pytest.mark.parametrize("weighted", [False, True])
 def test_forward_fp32_order_per_output_bruteforce(weighted):
     """Each output is the sequential FP32 sum of its terms in ascending channel
-    order, one rounding per term (Section 2.1, single precision): a pure-Python
-    loop over one output at a time, on real-valued data where the order
-    changes the rounding.  Weights are powers of two, so w * x is exact and the
-    fused multiply-add is one FP32 add of the product."""
+    order (Section 2.1, single precision): a pure-Python loop over one output
+    at a time, on real-valued data where the order changes the rounding.  A
+    weighted term is the FP32 product w * x, rounded, then added (the weight
+    is a gain on the data); with real-valued weights a fused multiply-add
+    rounds differently somewhere, which the loop would catch."""
     rng = np.random.default_rng(21)
     nc, nd, ns, nb = 9, 5, 23, 2
     delta, nin = _rand_case(rng, nc, nd, ns, 10)
     x = (rng.standard_normal((nb, nc, nin)) * 10.0 ** rng.integers(-3, 4, (nb, nc, nin))).astype(np.float32)
-    w = (2.0 ** rng.integers(-2, 3, nc)).astype(np.float32) if weighted else None
+    w = rng.uniform(0.3, 3.0, nc).astype(np.float32) if weighted else None
     out = oracle.forward_f32(x, delta, ns, w)
+    fused_differs = False
     for b in range(nb):
         for j in range(nd):
             for t in range(ns):
                 acc = np.float32(0.0)
+                facc = 0.0
                 for c in range(nc):
                     term = x[b, c, t + delta[j, c]]
                     if w is not None:
+                        # the fused form: w * x + acc exactly, then one rounding
+                        facc = float(np.float32(float(w[c]) * float(term) + float(facc)))
                         term = np.float32(w[c] * term)
                     acc = np.float32(acc + term)
                 assert out[b, j, t] == acc, (b, j, t)
+                fused_differs |= w is not None and np.float32(facc) != acc
+    if weighted:
+        assert fused_differs  # the data tells the two roundings apart
     # a different channel order rounds differently somewhere (the pin can fail)
     rev = oracle.forward_f32(x[:, ::-1].copy(), delta[:, ::-1].copy(), ns, None if w is None else w[::-1].copy())
     assert not np.array_equal(rev, out)
+
+
+def test_forward_weights_are_a_gain_on_the_input():
+    """Weighted dedispersion equals unweighted dedispersion of the input with
+    every channel row scaled by its weight in FP32 (the weight is a per-channel
+    gain), bit for bit, at the config-0 geometry with real-valued weights."""
+    rng = np.random.default_rng(22)
+    b = synth.config(0)[0]
+    delta = oracle.delay_table(b.freqs(), b.tsamp_s, b.dms())
+    nin = b.nsamp + int(delta.max())
+    x = rng.standard_normal((2, b.nchan, nin)).astype(np.float32)
+    w = rng.uniform(0.25, 2.0, b.nchan).astype(np.float32)
+    scaled = (w[None, :, None] * x).astype(np.float32)
+    assert np.array_equal(oracle.forward_f32(x, delta, b.nsamp, w), oracle.forward_f32(scaled, delta, b.nsamp))
+    pb = rng.integers(0, 2, 300).astype(np.int32)
+    pd = rng.integers(0, b.ndm, 300).astype(np.int32)
+    ps = rng.integers(0, b.nsamp, 300).astype(np.int32)
+    got, _ = oracle.forward_points(x, delta, pb, pd, ps, w)
+    ref, _ = oracle.forward_points(scaled, delta, pb, pd, ps)
+    assert np.array_equal(got, ref)
 
 
 def test_forward_dm0_is_channel_sum():
