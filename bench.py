@@ -44,6 +44,9 @@ def parse():
                     help="copy: a plain 1 GiB device copy, the reference for HBM byte counters")
     ap.add_argument("--no-tune", action="store_true", help="use default variants (no autotuning)")
     ap.add_argument("--variant", type=int, default=None, help="force a kernel variant (no autotuning)")
+    ap.add_argument("--queues", type=int, default=0, help="batched: force 1 or 8 work queues")
+    ap.add_argument("--weights", action="store_true",
+                    help="apertif: per-channel weights (all ones), i.e. the fused multiply-add path")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-beam loop")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
@@ -403,8 +406,11 @@ def measure(wl, args, steps, warmup, plain_loop=True):
         batch = dd.Batch(plans, xs, outs, tune=not args.no_tune and args.variant is None)
         if args.variant is not None:
             batch.set_variant(args.variant)
+        if args.queues:
+            batch.set_queues(args.queues)
         variant_name = dd.variant_names("f32")[batch.variant]
-        log(f"batch created: variant {batch.variant} {variant_name}")
+        extra["queues"] = batch.queues
+        log(f"batch created: variant {batch.variant} {variant_name}, {batch.queues} work queue(s)")
         step = batch.execute
         if plain_loop and not args.no_plain:
             if not args.no_tune and args.variant is None:
@@ -418,6 +424,7 @@ def measure(wl, args, steps, warmup, plain_loop=True):
         kernel_name = "win_persistent"
     elif wl in ("apertif", "lofar"):
         p, b, x, o = plans[0], beams[0], xs[0], outs[0]
+        wts = torch.ones(b.nchan, device=dev) if args.weights and b.dtype != "u8" else None
         if args.variant is not None:
             p.set_variant(args.variant, "u8" if b.dtype == "u8" else "f32")
             log(f"variant forced to {args.variant}")
@@ -427,8 +434,10 @@ def measure(wl, args, steps, warmup, plain_loop=True):
             log(f"autotuned: {times}")
 
         def step():
-            dd.dedisperse(x, p, nsamp=b.nsamp, out=o)
+            dd.dedisperse(x, p, wts, nsamp=b.nsamp, out=o)
         dt = "u8" if b.dtype == "u8" else "f32"
+        if wts is not None:
+            extra["weights"] = "ones (fused multiply-add per term)"
         vi = p.variant(dt)
         variant_name = dd.variant_names(dt)[vi] if vi >= 0 else "direct"
         kernel_name = ("direct_u8_kernel" if dt == "u8" else "direct_f32_kernel") if vi < 0 else \

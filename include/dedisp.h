@@ -233,6 +233,18 @@ dedisp_status dedisp_batch_set_variant(dedisp_batch batch, int32_t variant);
 /* The tiled variant the batch runs (-1 for a NULL batch). */
 int32_t dedisp_batch_variant(dedisp_batch batch);
 
+/* Work queues of the batch's persistent launch: 1 (one global order) or 8
+ * (one per XCD, each (beam, time tile) group in one queue, so the blocks
+ * that share an input window share that XCD's L2); the tuner keeps the
+ * faster (0 for a NULL batch). */
+int32_t dedisp_batch_queues(dedisp_batch batch);
+
+/* Rebuild the batch's work table with nqueue (1 or 8) queues, keeping its
+ * variant; drops the captured graph.  Waits for the device first.
+ * DEDISP_E_INVALID for another count.  Allocates; not for use under graph
+ * capture. */
+dedisp_status dedisp_batch_set_queues(dedisp_batch batch, int32_t nqueue);
+
 /* Wait for any replay of the batch still in flight, then free it. */
 dedisp_status dedisp_batch_destroy(dedisp_batch batch);
 

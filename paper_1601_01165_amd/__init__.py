@@ -480,6 +480,15 @@ class Batch:
         """Index of the FP32 tiled variant the batch runs."""
         return int(lib().dedisp_batch_variant(self._h))
 
+    @property
+    def queues(self) -> int:
+        """Work queues of the persistent launch (1, or 8: one per XCD)."""
+        return int(lib().dedisp_batch_queues(self._h))
+
+    def set_queues(self, n: int):
+        """Rebuild the work table with n (1 or 8) queues, keeping the variant."""
+        check(lib().dedisp_batch_set_queues(self._h, int(n)), "batch_set_queues")
+
     def set_variant(self, i: int):
         """Run the batch with FP32 tiled variant i (rebuilds its work table)."""
         check(lib().dedisp_batch_set_variant(self._h, int(i)), "batch_set_variant")

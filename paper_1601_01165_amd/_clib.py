@@ -37,6 +37,8 @@ SIGNATURES = {
     "dedisp_execute_per_beam": (i32, [vp, vp]),
     "dedisp_batch_set_variant": (i32, [vp, i32]),
     "dedisp_batch_variant": (i32, [vp]),
+    "dedisp_batch_queues": (i32, [vp]),
+    "dedisp_batch_set_queues": (i32, [vp, i32]),
     "dedisp_batch_destroy": (i32, [vp]),
     "dedisp_autotune": (i32, [vp, i32, i32, i32, cp]),
     "dedisp_autotune_times": (i32, [vp, i32, vp, i32]),

@@ -388,6 +388,8 @@ dedisp_status dedisp_batch_create(dedisp_batch* out, int32_t nbeam, const dedisp
   return DEDISP_OK;
 }
 
+int32_t dedisp_batch_queues(dedisp_batch b) { return b ? b->nqueue : 0; }
+
 dedisp_status dedisp_execute_batched(dedisp_batch b, void* stream) {
   if (!b) return fail(DEDISP_E_INVALID, "batch is NULL");
   if (b->variant < 0) return fail(DEDISP_E_INVALID, "batch has no work table (a variant change failed)");
@@ -440,6 +442,18 @@ dedisp_status dedisp_batch_set_variant(dedisp_batch b, int32_t variant) {
   if (e != hipSuccess) return hip_fail(e, "waiting for the batch before a variant change");
   drop_work(b);
   return build_work(b, variant);
+}
+
+dedisp_status dedisp_batch_set_queues(dedisp_batch b, int32_t nqueue) {
+  if (!b) return fail(DEDISP_E_INVALID, "batch is NULL");
+  if (nqueue != 1 && nqueue != kNumXcd) return fail(DEDISP_E_INVALID, "nqueue must be 1 or 8");
+  const int vi = b->variant;
+  if (vi < 0) return fail(DEDISP_E_INVALID, "batch has no work table");
+  const hipError_t e = wait_idle(b);
+  if (e != hipSuccess) return hip_fail(e, "waiting for the batch before a queue change");
+  drop_work(b);
+  b->nqueue = nqueue;
+  return build_work(b, vi);
 }
 
 int32_t dedisp_batch_variant(dedisp_batch b) { return b ? b->variant : -1; }

@@ -120,13 +120,16 @@ __device__ __forceinline__ float sload_f32(const float* p) {
 // ---------------------------------------------------------------------------
 
 // Stage input rows [c0, c0 + ncc) into LDS.  Wave w copies rows w, w + NWAVE, ...
-template <int NWAVE, int ROWCAP>
-__device__ __forceinline__ void stage_f32(float4* lds4, const float* in, const TileArgs& a, const int32_t* blk,
+// With weights each staged sample is the FP32 product w[c] * x (the weight is
+// a gain on the channel's data), so the sums themselves are plain adds.
+template <int NWAVE, int ROWCAP, bool WEIGHTED>
+__device__ __forceinline__ void stage_f32(int wave, float4* lds4, const float* in, const TileArgs& a, const int32_t* blk,
                                           int c0, int ncc, int t0) {
-  const int wave = wave_id(), lane = lane_fresh();
+  const int lane = lane_fresh();
   for (int cl = wave; cl < ncc; cl += NWAVE) {
     const int sb = blk[2 * (c0 + cl)];
     const int sl = blk[2 * (c0 + cl) + 1];
+    const float wc = WEIGHTED ? a.w_in[c0 + cl] : 1.f;
     const float* src = in + (int64_t)(c0 + cl) * a.in_stride + a.in_shift;
     const int u0 = t0 + sb;
     float4* dst = lds4 + cl * (ROWCAP / 4);
@@ -143,6 +146,12 @@ __device__ __forceinline__ void stage_f32(float4* lds4, const float* in, const T
         x.z = (u + 2 >= a.in_lo && u + 2 < a.in_hi) ? src[u + 2] : 0.f;
         x.w = (u + 3 >= a.in_lo && u + 3 < a.in_hi) ? src[u + 3] : 0.f;
       }
+      if (WEIGHTED) {
+        x.x = wc * x.x;
+        x.y = wc * x.y;
+        x.z = wc * x.z;
+        x.w = wc * x.w;
+      }
       dst[v] = x;
     }
   }
@@ -153,11 +162,11 @@ __device__ __forceinline__ void stage_f32(float4* lds4, const float* in, const T
 // resource covering its valid range, so positions outside it read as zero
 // without a branch (the adjoint relies on this for its virtual padding).
 template <int NWAVE, int ROWCAP>
-__device__ __forceinline__ void stage_f32_async(float4* lds4, const float* in, const TileArgs& a,
+__device__ __forceinline__ void stage_f32_async(int wave, float4* lds4, const float* in, const TileArgs& a,
                                                 const int32_t* blk, int c0, int ncc, int t0) {
   // whole 64-lane loads stay inside the row's LDS slot
   static_assert(ROWCAP % 256 == 0, "LDS rows hold a multiple of 64 float4");
-  const int wave = wave_id(), lane = lane_fresh();
+  const int lane = lane_fresh();
   for (int cl = wave; cl < ncc; cl += NWAVE) {
     const ent2_t bl = sload_entry2(blk + 2 * (c0 + cl));
     const int sb = bl[0];
@@ -176,24 +185,52 @@ __device__ __forceinline__ void stage_f32_async(float4* lds4, const float* in, c
 
 // Entries {stage base, stage length} of the rows wave w stages for the pass
 // starting at input row c0 (rows w, w + NWAVE, ...): lane 2k holds the base
-// of the wave's k-th row, lane 2k + 1 its length.  A vector load, issued a
-// pass ahead: the per-pass wait for the staged rows covers it, so staging
-// never stalls on a scalar-cache miss.
+// of the wave's k-th row, lane 2k + 1 its length and lane 32 + k its weight
+// (float bits; weighted kernels only).  A vector load, issued a pass ahead:
+// the per-pass wait for the staged rows covers it, so staging never stalls on
+// a scalar-cache miss.
 template <int NWAVE, int CC>
-__device__ __forceinline__ int32_t stage_entries(const int32_t* blk, int rows_in, int c0) {
+__device__ __forceinline__ int32_t stage_entries(int wave, const int32_t* blk, const float* w, int rows_in, int c0) {
   constexpr int RPW = (CC + NWAVE - 1) / NWAVE;
-  const int wave = wave_id(), lane = lane_fresh();
-  const int cl = wave + (lane >> 1) * NWAVE;
-  if (lane < 2 * RPW && cl < CC && c0 + cl < rows_in) return blk[2 * (c0 + cl) + (lane & 1)];
+  static_assert(2 * RPW <= 32, "entries and weights share one VGPR");
+  const int lane = lane_fresh();
+  if (lane < 32) {
+    const int cl = wave + (lane >> 1) * NWAVE;
+    if (lane < 2 * RPW && cl < CC && c0 + cl < rows_in) return blk[2 * (c0 + cl) + (lane & 1)];
+  } else if (w) {
+    const int cl = wave + (lane - 32) * NWAVE;
+    if (lane - 32 < RPW && cl < CC && c0 + cl < rows_in) return __float_as_int(w[c0 + cl]);
+  }
   return 0;
+}
+
+// Weighted kernels, asynchronous staging: once this wave's rows of a pass
+// have landed, scale them in place by their channel's weight (FP32 product,
+// the weight being a gain on the data), before the barrier that publishes the
+// pass.  `ent` holds the pass's entries and weights (stage_entries).
+template <int NWAVE, int ROWCAP>
+__device__ __forceinline__ void scale_rows(int wave, float4* lds4, int32_t ent, int ncc) {
+  for (int k = 0, cl = wave; cl < ncc; ++k, cl += NWAVE) {
+    const int lane = lane_fresh();
+    const int sl = __builtin_amdgcn_readlane(ent, 2 * k + 1);
+    const float wc = __int_as_float(__builtin_amdgcn_readlane(ent, 32 + k));
+    float4* row = lds4 + cl * (ROWCAP / 4);
+    for (int v = lane; v < (sl >> 2); v += 64) {
+      float4 x = row[v];
+      x.x = wc * x.x;
+      x.y = wc * x.y;
+      x.z = wc * x.z;
+      x.w = wc * x.w;
+      row[v] = x;
+    }
+  }
 }
 
 // stage_f32_async with the entries from stage_entries (no scalar loads).
 template <int NWAVE, int ROWCAP>
-__device__ __forceinline__ void stage_f32_async_pre(float4* lds4, const float* in, const TileArgs& a, int32_t ent,
+__device__ __forceinline__ void stage_f32_async_pre(int wave, float4* lds4, const float* in, const TileArgs& a, int32_t ent,
                                                     int c0, int ncc, int t0) {
   static_assert(ROWCAP % 256 == 0, "LDS rows hold a multiple of 64 float4");
-  const int wave = wave_id();
   for (int k = 0, cl = wave; cl < ncc; ++k, cl += NWAVE) {
     const int lane = lane_fresh();
     const int sb = __builtin_amdgcn_readlane(ent, 2 * k);
@@ -215,10 +252,10 @@ __device__ __forceinline__ void stage_f32_async_pre(float4* lds4, const float* i
 // from memory, the rest zero), whatever the hardware returned for it.  Only
 // the adjoint's range can end off a 16-byte boundary.
 template <int NWAVE, int ROWCAP>
-__device__ __forceinline__ void fix_tail_async(float4* lds4, const float* in, const TileArgs& a,
+__device__ __forceinline__ void fix_tail_async(int wave, float4* lds4, const float* in, const TileArgs& a,
                                                const int32_t* blk, int c0, int ncc, int t0) {
   if ((a.in_hi & 3) == 0) return;
-  const int wave = wave_id(), lane = lane_fresh();
+  const int lane = lane_fresh();
   const int hi4 = a.in_hi & ~3;
   for (int cl = wave; cl < ncc; cl += NWAVE) {
     const ent2_t bl = sload_entry2(blk + 2 * (c0 + cl));
@@ -238,10 +275,10 @@ __device__ __forceinline__ void fix_tail_async(float4* lds4, const float* in, co
 // Store a finished tile (adjoint: scaled by w_out, with the wave's partial
 // sums of x * G for the weight gradient).
 template <int TP, int DPW, int NWAVE, bool ADJ>
-__device__ __forceinline__ void win_store(const TileArgs& a, const v16f* acc, int tt, int rt, int beam) {
+__device__ __forceinline__ void win_store(int wave, const TileArgs& a, const v16f* acc, int tt, int rt, int beam) {
   constexpr int DT = NWAVE * DPW;
   const int t0 = tt * 64 * TP;
-  const int wave = wave_id(), lane = lane_fresh();
+  const int lane = lane_fresh();
   float* out = static_cast<float*>(a.out);
   const int tl = t0 + lane * TP;
 #pragma unroll
@@ -308,10 +345,10 @@ __device__ __forceinline__ void win_store(const TileArgs& a, const v16f* acc, in
 // the lanes above (DPP), so the rows never leave the registers.  Samples past
 // the series end read as -inf.
 template <int TP, int DPW, int NWAVE>
-__device__ __forceinline__ void det_store_f32(const TileArgs& a, const v16f* acc, int tt, int rt, int beam, int t0) {
+__device__ __forceinline__ void det_store_f32(int wave, const TileArgs& a, const v16f* acc, int tt, int rt, int beam, int t0) {
   constexpr int ST = 64 * TP;
   constexpr int DT = NWAVE * DPW;
-  const int wave = wave_id(), lane = lane_fresh();
+  const int lane = lane_fresh();
   const int nvalid = min(ST, a.det_nsamp - t0);
   const int pos0 = TP * lane;
   const bool owned = pos0 < a.tile_step;
@@ -342,7 +379,7 @@ __device__ __forceinline__ void det_store_f32(const TileArgs& a, const v16f* acc
 // are in flight while pass p is summed.
 template <int TP, int DPW, int NWAVE, int NWIN, int CC, int ROWCAP, int NBUF, bool WEIGHTED, bool ADJ,
           bool DET = false, int JMP = 0>
-__device__ __forceinline__ void win_tile(const TileArgs& a, int tt, int rt, int beam, float4* lds4) {
+__device__ __forceinline__ void win_tile(int wave, const TileArgs& a, int tt, int rt, int beam, float4* lds4) {
   constexpr int ST = 64 * TP;
   constexpr int DT = NWAVE * DPW;
   constexpr int NACC = TP * DPW / 16;
@@ -350,35 +387,36 @@ __device__ __forceinline__ void win_tile(const TileArgs& a, int tt, int rt, int 
   tt = __builtin_amdgcn_readfirstlane(tt);
   rt = __builtin_amdgcn_readfirstlane(rt);
   const int t0 = DET ? tt * a.tile_step : tt * ST;
-  const int wave = wave_id();
   const int wt = rt * NWAVE + wave;
   const float* in = static_cast<const float*>(a.in) + (int64_t)beam * a.in_beam_stride;
   const int32_t* __restrict__ blk = uniform_ptr(a.blk + (size_t)rt * a.rows_in * 2);
   const int32_t* __restrict__ wav = uniform_ptr(a.wav + (size_t)wt * a.rows_in * WI);
-  const float* w_in = WEIGHTED ? uniform_ptr(a.w_in) : nullptr;
+  const float* w_in = WEIGHTED ? a.w_in : nullptr;
   const uint32_t lds_base = (uint32_t)(uintptr_t)(LDS_AS float4*)(lds4);
 
   v16f acc[NACC];
 #pragma unroll
   for (int q = 0; q < NACC; ++q) acc[q] = (v16f)(0.f);
 
-  // The wave's table entry (and weight) of the current input row live in
-  // SGPRs; each step fetches the next row's through buffer resources (reads
-  // past the last row return zero), advancing the byte offsets itself.
+  // The wave's table entry of the current input row lives in SGPRs; each
+  // step fetches the next row's through a buffer resource (reads past the
+  // last row return zero), advancing the byte offset itself.  Weights were
+  // applied when the rows were staged, so the steps only add.
   typedef typename EntT<DPW>::type E;
   const __amdgpu_buffer_rsrc_t trs =
       __builtin_amdgcn_make_buffer_rsrc((void*)wav, (short)0, a.rows_in * WI * 4, 0x00020000);
-  const __amdgpu_buffer_rsrc_t wrs =
-      __builtin_amdgcn_make_buffer_rsrc((void*)w_in, (short)0, WEIGHTED ? a.rows_in * 4 : 0, 0x00020000);
+  const __amdgpu_buffer_rsrc_t wrs = __builtin_amdgcn_make_buffer_rsrc(nullptr, (short)0, 0, 0x00020000);
   uint32_t toff = WI * 4, woff = 4;
   E ea = sload_entry_t<E>(wav), eb;
-  float wa = WEIGHTED ? sload_f32(w_in) : 0.f, wb = 0.f;
+  float wa = 0.f, wb = 0.f;
   const int npass = (a.rows_in + CC - 1) / CC;
-  int32_t stg = 0;  // staging entries of the next pass (NBUF = 2)
+  int32_t stg = 0;      // staging entries (and weights) of the next pass (NBUF = 2)
+  int32_t stg_cur = 0;  // those of the pass being summed (weighted kernels)
   if (NBUF == 2) {
     __syncthreads();  // a previous tile of this block is done with the LDS rows
-    stage_f32_async<NWAVE, ROWCAP>(lds4, in, a, blk, 0, min(CC, a.rows_in), t0);
-    if (CC < a.rows_in) stg = stage_entries<NWAVE, CC>(blk, a.rows_in, CC);
+    stage_f32_async<NWAVE, ROWCAP>(wave, lds4, in, a, blk, 0, min(CC, a.rows_in), t0);
+    if (WEIGHTED) stg_cur = stage_entries<NWAVE, CC>(wave, blk, w_in, a.rows_in, 0);
+    if (CC < a.rows_in) stg = stage_entries<NWAVE, CC>(wave, blk, w_in, a.rows_in, CC);
   }
   for (int p = 0; p < npass; ++p) {
     const int c0 = p * CC;
@@ -386,38 +424,40 @@ __device__ __forceinline__ void win_tile(const TileArgs& a, int tt, int rt, int 
     const int bufrow = NBUF == 2 ? (p & 1) * CC : 0;
     if (NBUF == 1) {
       __syncthreads();  // the previous pass is done with the LDS rows
-      stage_f32<NWAVE, ROWCAP>(lds4, in, a, blk, c0, ncc, t0);
+      stage_f32<NWAVE, ROWCAP, WEIGHTED>(wave, lds4, in, a, blk, c0, ncc, t0);
       __syncthreads();
     } else {
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's rows of pass p have landed
-      fix_tail_async<NWAVE, ROWCAP>(lds4 + (p & 1) * CC * (ROWCAP / 4), in, a, blk, c0, ncc, t0);
+      fix_tail_async<NWAVE, ROWCAP>(wave, lds4 + (p & 1) * CC * (ROWCAP / 4), in, a, blk, c0, ncc, t0);
+      if (WEIGHTED) scale_rows<NWAVE, ROWCAP>(wave, lds4 + (p & 1) * CC * (ROWCAP / 4), stg_cur, ncc);
       __syncthreads();  // every wave's have; every wave is done with pass p - 1
       if (p + 1 < npass)
-        stage_f32_async_pre<NWAVE, ROWCAP>(lds4 + ((p + 1) & 1) * CC * (ROWCAP / 4), in, a, stg, c0 + CC,
+        stage_f32_async_pre<NWAVE, ROWCAP>(wave, lds4 + ((p + 1) & 1) * CC * (ROWCAP / 4), in, a, stg, c0 + CC,
                                            min(CC, a.rows_in - c0 - CC), t0);
-      if (p + 2 < npass) stg = stage_entries<NWAVE, CC>(blk, a.rows_in, c0 + 2 * CC);
+      if (WEIGHTED) stg_cur = stg;
+      if (p + 2 < npass) stg = stage_entries<NWAVE, CC>(wave, blk, w_in, a.rows_in, c0 + 2 * CC);
     }
     // LDS byte address of this lane's window in the pass's first row slot
     uint32_t row = lds_base + (uint32_t)(lane_fresh() * TP * 4) + (uint32_t)(bufrow * ROWCAP * 4);
     if constexpr (JMP) {
       // the whole pass in one block, each row's DM slots branching into static adds
       static_assert(HasJmpPass<TP, DPW, NWIN, CC>::value, "no jump-form pass for this shape");
-      JmpPass<TP, DPW, NWIN, CC, WEIGHTED, JMP == 2, ROWCAP>::run(acc, row, ncc, ea, trs, toff, wa, wrs, woff);
+      JmpPass<TP, DPW, NWIN, CC, false, JMP == 2, ROWCAP>::run(acc, row, ncc, ea, trs, toff, wa, wrs, woff);
     } else if constexpr (HasWinPass<TP, DPW, NWIN, CC>::value) {
       // the whole pass in one block, index mode on throughout
-      WinPass<TP, DPW, NWIN, CC, WEIGHTED, ROWCAP>::run(acc, row, ncc, ea, trs, toff, wa, wrs, woff);
+      WinPass<TP, DPW, NWIN, CC, false, ROWCAP>::run(acc, row, ncc, ea, trs, toff, wa, wrs, woff);
     } else {
       // two rows per iteration with the entry registers swapping roles, so
       // the next row's entry needs no copy
       int cl = 0;
       for (; cl + 1 < ncc; cl += 2) {
-        win_step<TP, DPW, NWIN, WEIGHTED>(acc, row + (uint32_t)ea[0] * 4u, ea, eb, trs, toff, wa, wb, wrs, woff);
+        win_step<TP, DPW, NWIN, false>(acc, row + (uint32_t)ea[0] * 4u, ea, eb, trs, toff, wa, wb, wrs, woff);
         row += ROWCAP * 4;
-        win_step<TP, DPW, NWIN, WEIGHTED>(acc, row + (uint32_t)eb[0] * 4u, eb, ea, trs, toff, wb, wa, wrs, woff);
+        win_step<TP, DPW, NWIN, false>(acc, row + (uint32_t)eb[0] * 4u, eb, ea, trs, toff, wb, wa, wrs, woff);
         row += ROWCAP * 4;
       }
       if (cl < ncc) {
-        win_step<TP, DPW, NWIN, WEIGHTED>(acc, row + (uint32_t)ea[0] * 4u, ea, eb, trs, toff, wa, wb, wrs, woff);
+        win_step<TP, DPW, NWIN, false>(acc, row + (uint32_t)ea[0] * 4u, ea, eb, trs, toff, wa, wb, wrs, woff);
         ea = eb;
         wa = wb;
       }
@@ -425,9 +465,9 @@ __device__ __forceinline__ void win_tile(const TileArgs& a, int tt, int rt, int 
   }
 
   if constexpr (DET)
-    det_store_f32<TP, DPW, NWAVE>(a, acc, tt, rt, beam, t0);
+    det_store_f32<TP, DPW, NWAVE>(wave, a, acc, tt, rt, beam, t0);
   else
-    win_store<TP, DPW, NWAVE, ADJ>(a, acc, tt, rt, beam);
+    win_store<TP, DPW, NWAVE, ADJ>(wave, a, acc, tt, rt, beam);
 }
 
 // Waves per SIMD that a jump-form variant's registers allow (its accumulators
@@ -451,7 +491,7 @@ __attribute__((amdgpu_waves_per_eu(win_waves_per_eu<TP, DPW, NWIN, CC, JMP, DET>
   __shared__ float4 lds4[NBUF * CC * ROWCAP / 4];
   const int nblk = a.n_time_tiles * a.n_row_tiles;
   const int W = xcd_remap(blockIdx.x, nblk);
-  win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, WEIGHTED, ADJ, DET, JMP>(a, W / a.n_row_tiles,
+  win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, WEIGHTED, ADJ, DET, JMP>(wave_id(), a, W / a.n_row_tiles,
                                                                              W % a.n_row_tiles, blockIdx.y, lds4);
 }
 
@@ -471,12 +511,13 @@ void win_persistent(const BeamDesc* __restrict__ beams,
   __shared__ float4 lds4[NBUF * CC * ROWCAP / 4];
   __shared__ int s_tile;
   const int home = blockIdx.x % kNumXcd;
+  const int wave = wave_id();
   for (int qi = 0; qi < kNumXcd; ++qi) {
     const int q = (home + qi) % kNumXcd;
     const int q0 = qoff[q], n = qoff[q + 1] - q0;
     for (;;) {
       __syncthreads();  // everyone is done with s_tile and the LDS rows
-      if (threadIdx.x == 0) s_tile = atomicAdd(counters + q * kCounterStride, 1);
+      if (wave == 0 && lane_fresh() == 0) s_tile = atomicAdd(counters + q * kCounterStride, 1);
       __syncthreads();
       const int k = __builtin_amdgcn_readfirstlane(s_tile);
       if (k >= n) break;
@@ -484,7 +525,7 @@ void win_persistent(const BeamDesc* __restrict__ beams,
       const int local = order[2 * (q0 + k) + 1];
       const TileArgs& a = beams[b].a;
       const int tt = local / a.n_row_tiles, rt = local % a.n_row_tiles;
-      win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, WEIGHTED, false, false, JMP>(a, tt, rt, 0, lds4);
+      win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, WEIGHTED, false, false, JMP>(wave, a, tt, rt, 0, lds4);
     }
   }
 }
@@ -1000,7 +1041,8 @@ __global__ __launch_bounds__(256) void direct_f32_kernel(const float* __restrict
   float acc = 0.f;
   for (int c = 0; c < nchan; ++c) {
     const float x = src[(int64_t)c * in_stride + drow[c]];
-    acc = WEIGHTED ? fmaf(w[c], x, acc) : acc + x;
+    const float term = WEIGHTED ? w[c] * x : x;  // the weighted sample, rounded
+    acc = acc + term;
   }
   out[(int64_t)b * out_beam_stride + (int64_t)j * out_stride + t] = acc;
 }
@@ -1111,7 +1153,11 @@ __global__ __launch_bounds__(256) void reduce_gradw_kernel(const double* __restr
   X(31, 20, 8, 8, 56, 4, 1792, 2, 2)  /* 64 DMs x 1280, jump full */ \
   X(32, 20, 4, 8, 40, 6, 1536, 2, 1)  /* 32 DMs x 1280, jump, 4 waves/SIMD */ \
   X(33, 20, 4, 4, 40, 3, 1536, 2, 1)  /* 16 DMs x 1280, jump, 4 waves/SIMD */ \
-  X(34, 20, 4, 16, 40, 8, 1792, 2, 1) /* 64 DMs x 1280, jump, 4 waves/SIMD */
+  X(34, 20, 4, 16, 40, 8, 1792, 2, 1) /* 64 DMs x 1280, jump, 4 waves/SIMD */ \
+  X(35, 20, 4, 16, 40, 10, 1792, 2, 1) /* 64 DMs x 1280, jump, 4 waves/SIMD */ \
+  X(36, 20, 4, 16, 40, 8, 1792, 2, 2) /* 64 DMs x 1280, jump full, 4 waves/SIMD */ \
+  X(37, 20, 4, 16, 44, 10, 1792, 2, 1) /* 64 DMs x 1280, jump, 4 waves/SIMD */ \
+  X(38, 20, 4, 16, 44, 8, 1792, 2, 1) /* 64 DMs x 1280, jump, 4 waves/SIMD */
 
 // (index, Q dwords per lane, DPW, NWAVE, CC rows per LDS pass, ROWCAP bytes)
 #define U8_VARIANTS(X)                                      \

@@ -414,6 +414,9 @@ JMP_VARIANTS = [
     (20, 4, 40, 3, 8),
     (20, 4, 40, 6, 8),
     (20, 4, 40, 8, 8),
+    (20, 4, 40, 10, 8),
+    (20, 4, 44, 8, 4),
+    (20, 4, 44, 10, 4),
 ]
 
 
@@ -453,7 +456,7 @@ def main(out_path):
         "    __amdgpu_buffer_rsrc_t wrs, uint32_t& woff);\n\n",
     ]
     for tp, dpw, nwin in VARIANTS:
-        for weighted in (False, True):
+        for weighted in (False,):
             parts.append(step(tp, dpw, nwin, weighted))
             parts.append("\n")
     parts += [
@@ -470,7 +473,7 @@ def main(out_path):
         parts.append(f"template <> struct HasWinPass<{tp}, {dpw}, {nwin}, {cc}> : std::true_type {{}};\n")
     parts.append("\n")
     for tp, dpw, nwin, cc in PASS_VARIANTS:
-        for weighted in (False, True):
+        for weighted in (False,):
             parts.append(pass_block(tp, dpw, nwin, cc, weighted))
             parts.append("\n")
     parts += [
@@ -495,7 +498,7 @@ def main(out_path):
     for jv in JMP_VARIANTS:
         tp, dpw, nwin, cc = jv[:4]
         acc0 = jv[4] if len(jv) > 4 else ACC0
-        for weighted in (False, True):
+        for weighted in (False,):
             for full in (False, True):
                 parts.append(jmp_pass(tp, dpw, nwin, cc, weighted, full, acc0))
                 parts.append("\n")

@@ -256,7 +256,7 @@ def test_config1_full_size_sampled():
     plan = dd.Plan(b.freqs(), b.tsamp_s, b.dms())
     _note(f"config1 default variant {plan.variant()}")
     # untuned, the plan takes the measured-fastest shape that fits this geometry
-    assert dd.variant_names("f32")[plan.variant()] == "win_tp20_dpw4_nw16_win40_cc8_buf2_jmp"
+    assert dd.variant_names("f32")[plan.variant()] == "win_tp20_dpw4_nw16_win40_cc10_buf2_jmp"
     xg = torch.from_numpy(x).cuda()[None][:, :, :nin]
     out = dd.dedisperse(xg, plan, nsamp=b.nsamp)
     torch.cuda.synchronize()
