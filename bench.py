@@ -315,7 +315,8 @@ def stored_traffic(workload, variant):
         if not ln.startswith("traffic "):
             continue
         kv = dict(tok.split("=", 1) for tok in ln.split()[1:])
-        if kv.get("workload") == workload and kv.get("variant") == variant and kv.get("sources") == want:
+        # variant names are stored with spaces as underscores (the line is whitespace-separated)
+        if kv.get("workload") == workload and kv.get("variant") == variant.replace(" ", "_") and kv.get("sources") == want:
             return float(kv["bytes_per_launch"])
     return None
 
