@@ -586,19 +586,29 @@ __device__ __forceinline__ void stage_u8(uint4* lds, const uint8_t* in, const Ti
 // a byte shift, so the data passes through registers: load() fetches a pass's
 // bytes into registers, store() writes the shifted copies to LDS.  The kernel calls load() for pass p + 1 before it
 // sums pass p, so the global loads are in flight during the adds.
+// With fewer rows than waves, the G = NWAVE / CC waves of a row take its
+// 16-byte chunks in turn (wave w: row w mod CC, chunks lane + 64 (w / CC +
+// G i)), so that every wave stages and each holds fewer chunks.
 template <int NWAVE, int CC, int ROWCAP, typename E>
 struct ShiftStage {
-  static constexpr int RPW = (CC + NWAVE - 1) / NWAVE;  // rows staged per wave
-  static constexpr int VPL = (ROWCAP / 16 + 63) / 64;   // 16-byte chunks per lane per row
+  static constexpr int G = CC < NWAVE ? NWAVE / CC : 1;  // waves per row
+  static_assert(CC >= NWAVE || NWAVE % CC == 0, "rows per pass must divide the waves");
+  static constexpr int RPW = (CC + NWAVE - 1) / NWAVE;        // rows staged per wave
+  static constexpr int VPL = (ROWCAP / 16 + 64 * G - 1) / (64 * G);  // 16-byte chunks per lane per row
   uint32_t d[RPW][VPL][5];
   int nv[RPW];
+
+  static __device__ __forceinline__ int row_of(int wave, int r) { return G > 1 ? wave % CC : wave + r * NWAVE; }
+  static __device__ __forceinline__ int chunk_of(int wave, int lane, int i) {
+    return G > 1 ? lane + 64 * (wave / CC + G * i) : lane + 64 * i;
+  }
 
   __device__ __forceinline__ void load(const uint8_t* in, const TileArgs& a, const int32_t* blk, const int32_t* wav,
                                        int c0, int ncc, int t0) {
     const int wave = wave_id(), lane = threadIdx.x & 63;
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
-      const int cl = wave + r * NWAVE;
+      const int cl = row_of(wave, r);
       nv[r] = 0;
       if (cl < ncc) {
         const ent2_t bl = sload_entry2(blk + 2 * (c0 + cl));
@@ -607,7 +617,7 @@ struct ShiftStage {
         nv[r] = bl[1] >> 4;
 #pragma unroll
         for (int i = 0; i < VPL; ++i) {
-          const int v = lane + 64 * i;
+          const int v = chunk_of(wave, lane, i);
           const int u = u0 + 16 * v;
           if (v < nv[r]) {
             if (u + 20 <= a.in_hi) {
@@ -640,10 +650,10 @@ struct ShiftStage {
     const int wave = wave_id(), lane = threadIdx.x & 63;
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
-      const int cl = wave + r * NWAVE;
+      const int cl = row_of(wave, r);
 #pragma unroll
       for (int i = 0; i < VPL; ++i) {
-        const int v = lane + 64 * i;
+        const int v = chunk_of(wave, lane, i);
         if (v < nv[r]) {
           const uint32_t* x = d[r][i];
           lds[(0 * CC + cl) * (ROWCAP / 16) + v] = make_uint4(x[0], x[1], x[2], x[3]);
@@ -900,7 +910,7 @@ __device__ __forceinline__ void u8s_tile(const TileArgs& a) {
       if (cl >= ncc) break;
 #pragma unroll
       for (int jj = 0; jj < DPW; ++jj) {
-        const uint32_t* pr = lds32 + off[cl * WI + jj];
+        const uint32_t* pr = reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(lds32) + off[cl * WI + jj]);
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
           const uint32_t v = pr[64 * q];
@@ -1009,12 +1019,16 @@ __device__ __forceinline__ void u8s_tile(const TileArgs& a) {
   }
 }
 
-template <int Q, int DPW, int NWAVE, int CC, int ROWCAP, bool WIDE>
-__global__ __launch_bounds__(64 * NWAVE) void u8s_kernel(TileArgs a) {
+// WPE > 0 asks the compiler to fit WPE waves per SIMD (512 / WPE registers),
+// so that as many blocks as the LDS allows stay resident on a CU.
+template <int Q, int DPW, int NWAVE, int CC, int ROWCAP, bool WIDE, int WPE>
+__global__ __launch_bounds__(64 * NWAVE) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1))) void u8s_kernel(
+    TileArgs a) {
   u8s_tile<Q, DPW, NWAVE, CC, ROWCAP, WIDE, false>(a);
 }
 
-// With the single-pulse search in the epilogue.
+// With the single-pulse search in the epilogue (no occupancy request: the
+// search needs its registers).
 template <int Q, int DPW, int NWAVE, int CC, int ROWCAP, bool WIDE>
 __global__ __launch_bounds__(64 * NWAVE) void u8s_det_kernel(TileArgs a) {
   u8s_tile<Q, DPW, NWAVE, CC, ROWCAP, WIDE, true>(a);
@@ -1174,18 +1188,20 @@ __global__ __launch_bounds__(256) void reduce_gradw_kernel(const double* __restr
   X(10, 2, 8, 4, 16, 1792, 2) /* 32 DMs x 512, async   */   \
   X(11, 2, 4, 4, 32, 1152, 2) /* 16 DMs x 512, async   */
 
-// Byte-shifted variants: (index, Q, DPW, NWAVE, CC, ROWCAP bytes per copy, WIDE)
-#define U8S_VARIANTS(X)                                      \
-  X(12, 4, 4, 4, 4, 1792, false) /* 16 DMs x 1024      */   \
-  X(13, 2, 4, 8, 4, 1792, false) /* 32 DMs x 512       */   \
-  X(14, 4, 4, 8, 8, 2304, false) /* 32 DMs x 1024      */   \
-  X(15, 4, 8, 4, 4, 2304, false) /* 32 DMs x 1024      */   \
-  X(16, 4, 4, 8, 4, 2304, false) /* 32 DMs x 1024      */   \
-  X(17, 4, 4, 4, 2, 1792, false) /* 16 DMs x 1024      */   \
-  X(18, 4, 4, 4, 4, 1792, true)  /* 16 DMs x 1024, wide */  \
-  X(19, 4, 4, 8, 4, 2304, true)  /* 32 DMs x 1024, wide */  \
-  X(20, 8, 4, 8, 4, 3328, false) /* 32 DMs x 2048      */   \
-  X(21, 4, 8, 8, 4, 3584, false) /* 64 DMs x 1024      */
+// Byte-shifted variants: (index, Q, DPW, NWAVE, CC, ROWCAP bytes per copy,
+// WIDE, waves per SIMD asked of the compiler or 0)
+#define U8S_VARIANTS(X)                                          \
+  X(12, 4, 4, 4, 4, 1792, false, 0) /* 16 DMs x 1024      */    \
+  X(13, 2, 4, 8, 4, 1792, false, 0) /* 32 DMs x 512       */    \
+  X(14, 4, 4, 8, 8, 2304, false, 0) /* 32 DMs x 1024      */    \
+  X(15, 4, 8, 4, 4, 2304, false, 0) /* 32 DMs x 1024      */    \
+  X(16, 4, 4, 8, 4, 2304, false, 0) /* 32 DMs x 1024      */    \
+  X(17, 4, 4, 4, 2, 1792, false, 0) /* 16 DMs x 1024      */    \
+  X(18, 4, 4, 4, 4, 1792, true, 0)  /* 16 DMs x 1024, wide */   \
+  X(19, 4, 4, 8, 4, 2304, true, 0)  /* 32 DMs x 1024, wide */   \
+  X(20, 8, 4, 8, 4, 3328, false, 0) /* 32 DMs x 2048      */    \
+  X(21, 4, 8, 8, 4, 3584, false, 0) /* 64 DMs x 1024      */    \
+  X(22, 4, 4, 16, 4, 3584, false, 8) /* 64 DMs x 1024, 2 blocks/CU */
 
 const std::vector<Variant>& variants_f32() {
   static const std::vector<Variant> v = [] {
@@ -1210,9 +1226,10 @@ const std::vector<Variant>& variants_u8() {
                       ID});
     U8_VARIANTS(MAKE_U8)
 #undef MAKE_U8
-#define MAKE_U8S(ID, Q, DPW, NW, CC, RC, WIDE)                                                               \
-  r.push_back(Variant{WIDE ? "u8s_q" #Q "_dpw" #DPW "_nw" #NW "_cc" #CC "_wide" : "u8s_q" #Q "_dpw" #DPW "_nw" #NW \
-                                                                                     "_cc" #CC,             \
+#define MAKE_U8S(ID, Q, DPW, NW, CC, RC, WIDE, WPE)                                                          \
+  r.push_back(Variant{WIDE        ? "u8s_q" #Q "_dpw" #DPW "_nw" #NW "_cc" #CC "_wide"                          \
+                      : WPE > 0   ? "u8s_q" #Q "_dpw" #DPW "_nw" #NW "_cc" #CC "_o" #WPE                        \
+                                  : "u8s_q" #Q "_dpw" #DPW "_nw" #NW "_cc" #CC,                                 \
                       KIND_TILE_U8, Q, DPW, NW, 0, CC, RC, 1, ID, WIDE ? 2 : 1});
     U8S_VARIANTS(MAKE_U8S)
 #undef MAKE_U8S
@@ -1254,9 +1271,9 @@ hipError_t launch_tiled(const Variant& v, const TileArgs& a, int nbeam, bool adj
   }
     U8_VARIANTS(LAUNCH_U8)
 #undef LAUNCH_U8
-#define LAUNCH_U8S(ID, Q, DPW, NW, CC, RC, WIDE)                                       \
-  if (v.id == ID) {                                                                    \
-    hipLaunchKernelGGL((u8s_kernel<Q, DPW, NW, CC, RC, WIDE>), grid, block, 0, s, a);  \
+#define LAUNCH_U8S(ID, Q, DPW, NW, CC, RC, WIDE, WPE)                                       \
+  if (v.id == ID) {                                                                         \
+    hipLaunchKernelGGL((u8s_kernel<Q, DPW, NW, CC, RC, WIDE, WPE>), grid, block, 0, s, a);  \
     return hipGetLastError();                                                          \
   }
     U8S_VARIANTS(LAUNCH_U8S)
@@ -1299,7 +1316,7 @@ hipError_t launch_detect(const Variant& v, const TileArgs& a, int nbeam, hipStre
     F32_VARIANTS(LAUNCH_DF)
 #undef LAUNCH_DF
   } else {
-#define LAUNCH_DU8(ID, Q, DPW, NW, CC, RC, WIDE)                                          \
+#define LAUNCH_DU8(ID, Q, DPW, NW, CC, RC, WIDE, WPE)                                     \
   if (v.id == ID) {                                                                       \
     hipLaunchKernelGGL((u8s_det_kernel<Q, DPW, NW, CC, RC, WIDE>), grid, block, 0, s, a);   \
     return hipGetLastError();                                                             \

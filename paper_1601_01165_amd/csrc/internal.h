@@ -51,7 +51,7 @@ struct Variant {
   int st() const { return kind == KIND_WIN_F32 ? 64 * tp : 256 * tp; }
   int dt() const { return nwave * dpw; }
   // ints per wave-table entry: f32 {win_start, nl, one offset per row} padded to 4/8/16; u8 packed u16
-  // offsets (mode 0) or one LDS dword offset per row (byte-shifted modes)
+  // offsets (mode 0) or one LDS byte offset per row (byte-shifted modes)
   int wav_ints() const {
     if (kind == KIND_WIN_F32) return dpw + 2 <= 4 ? 4 : dpw + 2 <= 8 ? 8 : 16;
     return mode == 0 ? 4 : (dpw <= 4 ? 4 : 8);
@@ -68,7 +68,7 @@ const std::vector<int>& default_order(int dir);
 //   blk[row_tile][rows_in]            {stage_base, stage_len}
 //   wav[wave_tile][rows_in][wav_ints] f32: {win_start, nl, offset of each row...} (jump form: offset times
 //                                      the block size)
-//                                      u8:  {packed u16 offsets...} or {LDS dword offset of each row...}
+//                                      u8:  {packed u16 offsets...} or {LDS byte offset of each row...}
 struct Tables {
   int variant = -1;
   int n_row_tiles = 0;

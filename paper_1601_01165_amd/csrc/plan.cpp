@@ -153,8 +153,8 @@ static bool build_tables(const Variant& v, int rows_out, int rows_in, const Dela
             if (v.mode == 0) {
               e[j / 2] |= (int32_t)((uint32_t)o << (16 * (j % 2)));
             } else {
-              // dword index into the staged copies: copy o & 3, row slot c % cc
-              e[j] = ((o & 3) * v.cc + c % v.cc) * (v.rowcap / 4) + (o >> 2);
+              // byte offset into the staged copies: copy o & 3, row slot c % cc, dword o >> 2
+              e[j] = 4 * (((o & 3) * v.cc + c % v.cc) * (v.rowcap / 4) + (o >> 2));
             }
             need = std::max(need, (o & ~3) + 256 * v.tp + 4);
           }
@@ -256,7 +256,7 @@ dedisp_status ensure_tables(dedisp_plan p, int dir, int vi, Tables** out) {
 const std::vector<int>& default_order(int dir) {
   static const std::vector<int> f32 = {35, 34, 37, 38, 36, 32, 33, 22, 28, 21, 29, 31, 23, 30, 19, 20, 25, 24, 27, 26, 15, 18, 13,
                                        17, 9,  8,  16, 6,  14, 11, 7,  12, 10, 2,  3,  0,  1,  5,  4};
-  static const std::vector<int> u8 = {16, 20, 15, 21, 12, 13, 17, 14, 18, 6, 2, 0, 5, 19, 9, 3, 4, 1, 8, 7, 10, 11};
+  static const std::vector<int> u8 = {22, 16, 20, 15, 21, 12, 13, 17, 14, 18, 6, 2, 0, 5, 19, 9, 3, 4, 1, 8, 7, 10, 11};
   static const std::vector<int> adj = {37, 38, 26, 27, 32, 34, 35, 36, 33, 19, 21, 29, 20, 30, 9, 8, 6, 11, 12, 7, 10, 13, 22, 28,
                                        18, 15, 23, 31, 17, 16, 25, 24, 14, 2, 3, 1, 0, 5, 4};
   return dir == 1 ? u8 : dir == 2 ? adj : f32;

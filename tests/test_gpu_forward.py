@@ -283,7 +283,7 @@ def test_config2_full_size_sampled():
     x = synth.noise(b, nin, synth.padded_len(nin, 1))
     plan = dd.Plan(b.freqs(), b.tsamp_s, b.dms())
     _note(f"config2 default u8 variant {plan.variant('u8')}")
-    assert dd.variant_names("u8")[plan.variant("u8")] == "u8s_q4_dpw4_nw8_cc4"
+    assert dd.variant_names("u8")[plan.variant("u8")] == "u8s_q4_dpw4_nw16_cc4_o8"
     xg = torch.from_numpy(x).cuda()[None][:, :, :nin]
     out = dd.dedisperse(xg, plan, nsamp=b.nsamp)
     torch.cuda.synchronize()
