@@ -109,6 +109,25 @@ __device__ __forceinline__ ent16_t sbload16(__amdgpu_buffer_rsrc_t rs, uint32_t 
   asm volatile("s_buffer_load_dwordx16 %0, %1, %2\n\ts_waitcnt lgkmcnt(0)" : "=s"(r) : "s"(rs), "s"(off));
   return r;
 }
+__device__ __forceinline__ ent4_t sbload4(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  ent4_t r;
+  asm volatile("s_buffer_load_dwordx4 %0, %1, %2\n\ts_waitcnt lgkmcnt(0)" : "=s"(r) : "s"(rs), "s"(off));
+  return r;
+}
+template <typename E>
+__device__ __forceinline__ E sbload_t(__amdgpu_buffer_rsrc_t rs, uint32_t off);
+template <>
+__device__ __forceinline__ ent4_t sbload_t<ent4_t>(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  return sbload4(rs, off);
+}
+template <>
+__device__ __forceinline__ ent8_t sbload_t<ent8_t>(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  return sbload8(rs, off);
+}
+template <>
+__device__ __forceinline__ ent16_t sbload_t<ent16_t>(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  return sbload16(rs, off);
+}
 __device__ __forceinline__ float sload_f32(const float* p) {
   float r;
   asm volatile("s_load_dword %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(r) : "s"(p));
@@ -412,13 +431,34 @@ __device__ __forceinline__ void win_tile(int wave, const TileArgs& a, int tt, in
   const int npass = (a.rows_in + CC - 1) / CC;
   int32_t stg = 0;      // staging entries (and weights) of the next pass (NBUF = 2)
   int32_t stg_cur = 0;  // those of the pass being summed (weighted kernels)
-  if (NBUF == 2) {
-    __syncthreads();  // a previous tile of this block is done with the LDS rows
-    stage_f32_async<NWAVE, ROWCAP>(wave, lds4, in, a, blk, 0, min(CC, a.rows_in), t0);
-    if (WEIGHTED) stg_cur = stage_entries<NWAVE, CC>(wave, blk, w_in, a.rows_in, 0);
-    if (CC < a.rows_in) stg = stage_entries<NWAVE, CC>(wave, blk, w_in, a.rows_in, CC);
+  // Adjoint: the input rows (DM trials) of the passes at either end may stage
+  // windows that all miss the valid samples [in_lo, in_hi) of the output
+  // gradient (only zeros would be added); the tile runs from its first to
+  // its last pass that meets them (all passes when no span table is given).
+  int p_lo = 0, p_hi = npass - 1;
+  if constexpr (ADJ) {
+    if (a.span) {
+      const int32_t* sp = uniform_ptr(a.span + (size_t)rt * npass * 2);
+      auto live = [&](int q) {
+        const ent2_t e = sload_entry2(sp + 2 * q);
+        return t0 + e[0] < a.in_hi && t0 + e[1] > a.in_lo;
+      };
+      while (p_lo <= p_hi && !live(p_lo)) ++p_lo;
+      while (p_hi > p_lo && !live(p_hi)) --p_hi;
+      if (p_lo > 0) {
+        toff = (uint32_t)((p_lo * CC + 1) * WI * 4);
+        ea = sbload_t<E>(trs, (uint32_t)(p_lo * CC * WI * 4));
+      }
+    }
   }
-  for (int p = 0; p < npass; ++p) {
+  if (NBUF == 2 && p_lo <= p_hi) {
+    __syncthreads();  // a previous tile of this block is done with the LDS rows
+    stage_f32_async<NWAVE, ROWCAP>(wave, lds4 + (p_lo & 1) * CC * (ROWCAP / 4), in, a, blk, p_lo * CC,
+                                   min(CC, a.rows_in - p_lo * CC), t0);
+    if (WEIGHTED) stg_cur = stage_entries<NWAVE, CC>(wave, blk, w_in, a.rows_in, p_lo * CC);
+    if (p_lo < p_hi) stg = stage_entries<NWAVE, CC>(wave, blk, w_in, a.rows_in, (p_lo + 1) * CC);
+  }
+  for (int p = p_lo; p <= p_hi; ++p) {
     const int c0 = p * CC;
     const int ncc = min(CC, a.rows_in - c0);
     const int bufrow = NBUF == 2 ? (p & 1) * CC : 0;
@@ -431,11 +471,11 @@ __device__ __forceinline__ void win_tile(int wave, const TileArgs& a, int tt, in
       fix_tail_async<NWAVE, ROWCAP>(wave, lds4 + (p & 1) * CC * (ROWCAP / 4), in, a, blk, c0, ncc, t0);
       if (WEIGHTED) scale_rows<NWAVE, ROWCAP>(wave, lds4 + (p & 1) * CC * (ROWCAP / 4), stg_cur, ncc);
       __syncthreads();  // every wave's have; every wave is done with pass p - 1
-      if (p + 1 < npass)
+      if (p + 1 <= p_hi)
         stage_f32_async_pre<NWAVE, ROWCAP>(wave, lds4 + ((p + 1) & 1) * CC * (ROWCAP / 4), in, a, stg, c0 + CC,
                                            min(CC, a.rows_in - c0 - CC), t0);
       if (WEIGHTED) stg_cur = stg;
-      if (p + 2 < npass) stg = stage_entries<NWAVE, CC>(wave, blk, w_in, a.rows_in, c0 + 2 * CC);
+      if (p + 2 <= p_hi) stg = stage_entries<NWAVE, CC>(wave, blk, w_in, a.rows_in, c0 + 2 * CC);
     }
     // LDS byte address of this lane's window in the pass's first row slot
     uint32_t row = lds_base + (uint32_t)(lane_fresh() * TP * 4) + (uint32_t)(bufrow * ROWCAP * 4);
@@ -491,8 +531,13 @@ __attribute__((amdgpu_waves_per_eu(win_waves_per_eu<TP, DPW, NWIN, CC, JMP, DET>
   __shared__ float4 lds4[NBUF * CC * ROWCAP / 4];
   const int nblk = a.n_time_tiles * a.n_row_tiles;
   const int W = xcd_remap(blockIdx.x, nblk);
-  win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, WEIGHTED, ADJ, DET, JMP>(wave_id(), a, W / a.n_row_tiles,
-                                                                             W % a.n_row_tiles, blockIdx.y, lds4);
+  // Forward: the row tiles of one time tile run on one XCD (they share its
+  // input window in that L2).  Adjoint: the time tiles of one row tile do
+  // instead, so that the passes skipped near both ends of the output (see
+  // win_tile) are spread over every XCD rather than idling the first and last.
+  const int tt = ADJ ? W % a.n_time_tiles : W / a.n_row_tiles;
+  const int rt = ADJ ? W / a.n_time_tiles : W % a.n_row_tiles;
+  win_tile<TP, DPW, NWAVE, NWIN, CC, ROWCAP, NBUF, WEIGHTED, ADJ, DET, JMP>(wave_id(), a, tt, rt, blockIdx.y, lds4);
 }
 
 // Persistent form for batches of beams.  The work table is split into one

@@ -76,6 +76,7 @@ struct Tables {
   int max_stage = 0;
   int32_t* d_blk = nullptr;
   int32_t* d_wav = nullptr;
+  int32_t* d_span = nullptr;  // adjoint: per (row tile, pass) {least stage base, greatest stage end}
   size_t bytes = 0;
   int pins = 0;  // batches whose work table points at these tables (never freed while pinned)
 };
@@ -110,6 +111,7 @@ struct TileArgs {
   int tiles_per_block;       // time tiles walked by one block (uint8 double-buffered kernels)
   const int32_t* blk;
   const int32_t* wav;
+  const int32_t* span;       // adjoint: per (row tile, pass) {least stage base, greatest stage end}, or null
   const float* w_in;         // per input-row weight or null
   void* out;
   int64_t out_stride;

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <climits>
 #include <atomic>
 #include <cstdio>
 #include <functional>
@@ -185,6 +186,7 @@ static bool build_tables(const Variant& v, int rows_out, int rows_in, const Dela
 static void free_tables(Tables& t) {
   if (t.d_blk) (void)hipFree(t.d_blk);
   if (t.d_wav) (void)hipFree(t.d_wav);
+  if (t.d_span) (void)hipFree(t.d_span);
   t = Tables();
 }
 
@@ -228,16 +230,38 @@ dedisp_status ensure_tables(dedisp_plan p, int dir, int vi, Tables** out) {
     ok = build_tables(v, D, C, [&](int r, int c) { return del[(size_t)r * C + c]; }, blk, wav, nrt, maxs, why);
   }
   if (!ok) return fail(DEDISP_E_UNTUNED, std::string(v.name) + ": " + why);
+  // The adjoint's input rows (DM trials) reach outside the output gradient's
+  // samples for part of the time tiles: the span of each pass's staged
+  // windows lets the kernel skip passes that would add only zeros.
+  std::vector<int32_t> span;
+  if (dir == 2) {
+    const int rows_in = D, npass = (rows_in + v.cc - 1) / v.cc;
+    span.assign((size_t)nrt * npass * 2, 0);
+    for (int rt = 0; rt < nrt; ++rt)
+      for (int q = 0; q < npass; ++q) {
+        int smin = INT32_MAX, emax = INT32_MIN;
+        for (int c = q * v.cc; c < std::min(rows_in, (q + 1) * v.cc); ++c) {
+          const int32_t* b = &blk[((size_t)rt * rows_in + c) * 2];
+          smin = std::min(smin, b[0]);
+          emax = std::max(emax, b[0] + b[1]);
+        }
+        span[((size_t)rt * npass + q) * 2 + 0] = smin;
+        span[((size_t)rt * npass + q) * 2 + 1] = emax;
+      }
+  }
   Tables t;
   t.variant = vi;
   t.n_row_tiles = nrt;
   t.n_wave_tiles = nrt * v.nwave;
   t.max_stage = maxs;
-  t.bytes = (blk.size() + wav.size()) * sizeof(int32_t);
+  t.bytes = (blk.size() + wav.size() + span.size()) * sizeof(int32_t);
   hipError_t e = hipMalloc(&t.d_blk, blk.size() * sizeof(int32_t));
   if (e == hipSuccess) e = hipMalloc(&t.d_wav, wav.size() * sizeof(int32_t));
+  if (e == hipSuccess && !span.empty()) e = hipMalloc(&t.d_span, span.size() * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemcpy(t.d_blk, blk.data(), blk.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(t.d_wav, wav.data(), wav.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !span.empty())
+    e = hipMemcpy(t.d_span, span.data(), span.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     free_tables(t);
     return e == hipErrorOutOfMemory ? fail(DEDISP_E_NOMEM, "device allocation of tile tables failed")
@@ -353,6 +377,7 @@ static dedisp_status adjoint_impl(dedisp_plan p, int32_t nbeam, int32_t nsamp, i
     a.n_row_tiles = t->n_row_tiles;
     a.blk = t->d_blk;
     a.wav = t->d_wav;
+    a.span = t->d_span;
     a.w_in = nullptr;
     a.out = d_grad_in;
     a.out_stride = gi_stride;
